@@ -1,0 +1,318 @@
+/*
+ * bfpmg.h — block-floating-point (BFP) vector operations and multigrid on
+ * AMD MI355X (gfx950).
+ *
+ * Method: N. Kohl, S. F. McCormick, R. Tamstorf, "Multigrid methods using
+ * Block Floating Point Arithmetic". A BFP block is the tuple (e, m, w, d) of
+ * Section 2: one shared integer exponent e for a whole vector or matrix and
+ * w-bit two's-complement integer mantissas m, representing 2^e * m. Right
+ * shifts round toward minus infinity (floor).
+ *
+ * Conventions for every function below
+ *   - Return value: BFP_OK (0) or a negative bfp_status; BFP_PENDING (1) only
+ *     from mg_server_poll. bfp_last_error() describes the last failure of the
+ *     calling thread. No exception crosses this interface.
+ *   - Pointers named *_dev, bfp_vec.mant and bfp_vec.meta are device pointers
+ *     owned by the caller; the library never frees caller memory. Host
+ *     structs are read during the call only and may be reused afterwards.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Every operation is asynchronous on that stream; exponents, norms and
+ *     estimates stay in device memory, so no call below synchronizes with
+ *     the host except where stated.
+ *   - Shape, width and argument errors are detected on the host before any
+ *     launch; on error nothing is enqueued and nothing is written.
+ *   - Calls that write the same block must not overlap in time (different
+ *     streams without ordering); blocks that are only read may be shared.
+ */
+#ifndef BFPMG_H
+#define BFPMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BFP_OK = 0,
+  BFP_EINVAL = -1,     /* bad argument (null pointer, bad enum, aliasing)      */
+  BFP_EWIDTH = -2,     /* width outside 1..storage bits, or an exact product   */
+                       /* that could exceed the 62-bit integer budget          */
+  BFP_ESHAPE = -3,     /* grids of incompatible size / layout                  */
+  BFP_ENONFINITE = -4, /* NaN or Inf in FP64 input (reported by bfp_vec_check) */
+  BFP_ENOMEM = -5,     /* arena too small                                      */
+  BFP_EHIP = -6,       /* a HIP runtime call failed                            */
+  BFP_EBUSY = -7,      /* server admission queue full                          */
+  BFP_ENOTFOUND = -8,  /* unknown ticket                                       */
+  BFP_PENDING = 1      /* request not finished yet                             */
+} bfp_status;
+
+/* How an exact result z* is quantized to w_out bits.
+ *  BFP_NORMALIZE — qcomp (Algorithm 1): normalized result, exact up to w_out
+ *     bits: e_out = e_z* + mu* - w_out with mu* = max(1, max_i msb(z*_i)),
+ *     m_i = floor(z*_i / 2^(mu* - w_out)). Independent of any estimate.
+ *     Implemented as two passes over the inputs (the "compute twice"
+ *     strategy of Section 4): the first finds mu*, the second writes.
+ *  BFP_SATURATE — nnqcomp (Algorithm 3): e_out = floor(log2 gamma) + 2 - w_out
+ *     from the estimate gamma alone, m_i = clamp(floor(z*_i 2^(e_z*-e_out)),
+ *     X_w_out). One pass. A zero gamma gives e_out = e_z* + 1 - w_out. */
+typedef enum { BFP_NORMALIZE = 0, BFP_SATURATE = 1 } bfp_mode;
+
+/* Device metadata of a block: BFP_META_SLOTS int64 values.
+ *   [BFP_META_EXP] shared exponent e
+ *   [BFP_META_MAX] largest mantissa, [BFP_META_MIN] smallest mantissa
+ *                  (both taken over the whole padded array, ring included,
+ *                  so MAX >= 0 >= MIN and ||x||_inf = max(MAX, -MIN) * 2^e)
+ *   [BFP_META_SAT] entries saturated by the operation that wrote the block
+ *   [BFP_META_MU]  mu* of the last BFP_NORMALIZE operation writing the block
+ *   [BFP_META_FLAGS] bit 0: non-finite FP64 input seen by bfp_vec_from_f64
+ *   slots 8..15 are the library's reduction scratch; bfp_vec_init (or a
+ *   zero fill followed by bfp_meta_reset) must prepare them once. */
+#define BFP_META_SLOTS 16
+#define BFP_META_EXP 0
+#define BFP_META_MAX 1
+#define BFP_META_MIN 2
+#define BFP_META_SAT 3
+#define BFP_META_MU 4
+#define BFP_META_FLAGS 5
+
+/* One BFP block on a padded vertex-centred grid (D1 of Section 2: one
+ * exponent for the whole block). The grid has n interior points per
+ * dimension and a ring of Dirichlet boundary points that always holds zero
+ * mantissas: (n+2)^ndim points, x fastest. Storage is row-pitched: the
+ * (n+2)^(ndim-1) rows (y, or z-then-y) each hold `pitch` elements, of which
+ * the first n+2 are the grid row and the rest are zero padding. Use
+ * bfp_layout() for pitch and size. */
+typedef struct {
+  void* mant;           /* device, int8/int16/int32 per storage_bits        */
+  int64_t* meta;        /* device, BFP_META_SLOTS int64                      */
+  int32_t w;            /* mantissa width, 1 <= w <= storage_bits            */
+  int32_t storage_bits; /* 8, 16 or 32                                       */
+  int32_t ndim;         /* 2 or 3                                            */
+  int32_t n;            /* interior points per dimension (>= 1)              */
+  int64_t pitch;        /* elements per row, from bfp_layout                 */
+} bfp_vec;
+
+/* A BFP scalar (block of size one): value m * 2^exp, |m| < 2^(w-1). */
+typedef struct {
+  int64_t m;
+  int64_t exp;
+  int32_t w;
+} bfp_scalar;
+
+/* A constant-coefficient BFP matrix on padded grids (a sparse matrix with
+ * one shared exponent, D9): tap mantissas at offsets o in {-1,0,1}^ndim,
+ * index ((oz+1)*3 + (oy+1))*3 + (ox+1) (2D: (oy+1)*3 + (ox+1)).
+ *   BFP_STENCIL_A  same grid:       z[p] = sum_o t[o] x[p + o]
+ *   BFP_STENCIL_R  fine -> coarse:  z[I] = sum_o t[o] x[2I + o]
+ *   BFP_STENCIL_P  coarse -> fine:  z[p] = sum_o t[o] u[p + o], u the coarse
+ *                  block placed on the even fine nodes, zero elsewhere.
+ * Only interior output points are computed; the output ring stays zero. */
+typedef enum { BFP_STENCIL_A = 0, BFP_STENCIL_R = 1, BFP_STENCIL_P = 2 } bfp_stencil_kind;
+typedef struct {
+  int32_t ndim;
+  int32_t kind;
+  int64_t exp;
+  int32_t w;            /* max msb of the taps (bound used by width checks) */
+  int32_t taps[27];
+} bfp_stencil;
+
+/* The estimate gamma >= ||z||_inf needed by BFP_SATURATE (Table 1). Only
+ * floor(log2 gamma) matters. Norms are read from device metadata, so the
+ * estimate is evaluated on the device when the operation runs.
+ *   BFP_GAMMA_NORM     gamma = c * ||a||_inf           (c > 0)
+ *   BFP_GAMMA_SUM      gamma = ||a||_inf + ||b||_inf
+ *   BFP_GAMMA_EXPLICIT gamma = c                        (c >= 0)        */
+typedef enum { BFP_GAMMA_NORM = 1, BFP_GAMMA_SUM = 2, BFP_GAMMA_EXPLICIT = 3 } bfp_gamma_rule;
+typedef struct {
+  int32_t rule;
+  const int64_t* a_meta; /* device meta of the block in the first norm     */
+  const int64_t* b_meta; /* device meta of the block in the second norm    */
+  bfp_scalar c;          /* multiplier (NORM) or value (EXPLICIT), |m| < 2^24 */
+} bfp_gamma;
+
+/* ------------------------------------------------------------ layout --- */
+
+/* Row pitch (elements, a multiple of 16 bytes) and byte size of a block.  */
+int bfp_layout(int ndim, int n, int storage_bits, int64_t* pitch, size_t* bytes);
+
+/* Make v the zero block: all mantissas (ring and padding included) 0,
+ * e = 1 - w, MAX = MIN = 0, counters and reduction scratch reset.        */
+int bfp_vec_init(const bfp_vec* v, void* stream);
+
+/* Declare that v's mantissas, written by the caller (each in X_w, ring and
+ * padding zero), carry the exponent `exp`: sets e and recomputes MAX / MIN
+ * on the device. The mantissas are left unchanged.                        */
+int bfp_vec_assign(bfp_vec* v, int64_t exp, void* stream);
+
+/* Reset only the metadata reduction scratch of `meta` (after the caller
+ * filled the slots some other way).                                      */
+int bfp_meta_reset(int64_t* meta_dev, void* stream);
+
+/* ---------------------------------------------------------- a1: quant --- */
+
+/* dst = Q_w(src * 2^log2_scale): normalized floor quantization of exact FP64
+ * values (the `quant` steps of IR, V and FMG; rounding = floor as for every
+ * truncation in Section 2): e = max_i nu(x_i) - w, m_i = floor(x_i / 2^e),
+ * where nu(q) is the smallest b with -2^(b-1) <= q < 2^(b-1). An all-zero
+ * input gets e = 1 - w + log2_scale. src_dev is dense (n+2)^ndim FP64 in
+ * x-fastest order; ring values are ignored (the ring stays zero). A NaN or
+ * Inf sets bit 0 of meta[BFP_META_FLAGS]; bfp_vec_check reports it. Two
+ * launches (a max-reduction, then the conversion).                        */
+int bfp_vec_from_f64(const double* src_dev, int64_t log2_scale, bfp_vec* dst, void* stream);
+
+/* dst_dev (dense (n+2)^ndim FP64) = m * 2^e; exact for w <= 53 whenever the
+ * results are normal doubles.                                             */
+int bfp_vec_to_f64(const bfp_vec* src, double* dst_dev, void* stream);
+
+/* Synchronizes `stream`; BFP_ENONFINITE if v's non-finite flag is set.    */
+int bfp_vec_check(const bfp_vec* v, void* stream);
+
+/* ------------------------------------------- a2-a4: gemv and special cases */
+
+/* z = alpha * A x + beta * y (gemv, equation (4.1) of Section 4, computed by
+ * the exact gemv setup/row of Appendix B and quantized by `mode`); with
+ * y == NULL it is the exact SpMV z = alpha * A x (espmv). A is a stencil
+ * (A, R or P); x must be on A's input grid, y and z on its output grid.
+ * Exact intermediates: |alpha_m| * sum|taps| * 2^(w_x-1) and
+ * |beta_m| * 2^(w_y-1) must stay below 2^61 (else BFP_EWIDTH). z may alias
+ * y but not x. gamma is read only in BFP_SATURATE mode.                   */
+int bfp_stencil_apply(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar* alpha,
+                      const bfp_scalar* beta, const bfp_vec* y, int w_out, int mode,
+                      const bfp_gamma* gamma, bfp_vec* z, void* stream);
+
+/* r = A x - b (the IR and V-cycle residuals of Appendix C).               */
+int bfp_residual(const bfp_stencil* A, const bfp_vec* x, const bfp_vec* b, int w_out,
+                 int mode, const bfp_gamma* gamma, bfp_vec* r, void* stream);
+
+/* z = alpha * x + beta * y (exact axpby setup/row, Appendix B). z may alias
+ * x or y.                                                                 */
+int bfp_axpy(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta,
+             const bfp_vec* y, int w_out, int mode, const bfp_gamma* gamma, bfp_vec* z,
+             void* stream);
+
+/* z = x - y aligned at min(e_x, e_y) (the qsub of IR, Appendix C).          */
+int bfp_sub(const bfp_vec* x, const bfp_vec* y, int w_out, int mode, const bfp_gamma* gamma,
+            bfp_vec* z, void* stream);
+
+/* ---------------------------------------------------------- a5: dot ----- */
+
+/* Exact dot product sum_i x_m,i * y_m,i (Section 2 remark on BFP dot
+ * products: no alignment shifts, exponent e_x + e_y, accumulator growing
+ * with log2 n). out_dev: 8 int64, of which [0] = low and [1] = high 64 bits
+ * of the two's-complement 128-bit mantissa, [2] = exponent; [3..7] are the
+ * library's reduction scratch and must be zero before the first call (they
+ * are left zero after every call).                                        */
+int bfp_dot(const bfp_vec* x, const bfp_vec* y, int64_t* out_dev, void* stream);
+
+/* ------------------------------------------------ a7, a8: requantization */
+
+/* out = qcomp of the copy of in to w_out bits (normalized, floor): one pass,
+ * mu* comes from in's MAX / MIN metadata. out may alias in.              */
+int bfp_normalize(const bfp_vec* in, int w_out, bfp_vec* out, void* stream);
+
+/* out = nnqcomp of the copy of in: exponent from gamma, floor shift,
+ * saturation to X_w_out (Algorithm 3). out may alias in.                 */
+int bfp_saturate_truncate(const bfp_vec* in, int w_out, const bfp_gamma* gamma, bfp_vec* out,
+                          void* stream);
+
+/* ------------------------------------------------------ multigrid ------ */
+
+/* Exact Chebyshev coefficients (algorithm "Coefficients for two Chebyshev
+ * iterations", Appendix C) for rho = rho_num/rho_den and eta =
+ * eta_num/eta_den, multiplied by (scale_num/scale_den) for c1 and its square
+ * for c2 (the rescaling to a stored operator whose diagonal is
+ * scale_den/scale_num), each floor-quantized normalized to w bits.       */
+int bfp_cheby_coeffs(int64_t rho_num, int64_t rho_den, int64_t eta_num, int64_t eta_den,
+                     int64_t scale_num, int64_t scale_den, int w, bfp_scalar* c1,
+                     bfp_scalar* c2);
+
+/* Quantization policy of the solver: which calls use BFP_NORMALIZE.        */
+typedef enum {
+  MG_POLICY_Q = 0,              /* every call qcomp                          */
+  MG_POLICY_NN = 1,             /* every call nnqcomp (Section 6.4)          */
+  MG_POLICY_NN_IR_FIRST_Q = 2,  /* qcomp for the first IR residual per level */
+  MG_POLICY_NN_IR_FIRST2_Q = 3, /* ... and the first two of a plain IR solve */
+  MG_POLICY_NN_IR_Q = 4         /* qcomp for every IR residual               */
+} mg_policy;
+
+#define MG_MAX_LEVELS 16
+
+/* Problem and schedule of one solve: -Laplace u = f on the unit square
+ * (ndim 2, 5-point) or cube (ndim 3, 7-point), homogeneous Dirichlet,
+ * levels 1..L with n_j = 2^j - 1. Widths are indexed by level j (entry 0
+ * unused): w_check for A and b, w_work for the iterate x, w_inner for the
+ * V-cycle (the three precisions of Section 5).                            */
+typedef struct {
+  int32_t ndim, L;
+  int32_t nu1, nu2;   /* V(nu1, nu2); nu1 >= 1. The paper's cycle is V(1,0) */
+  int32_t N;          /* IR-V iterations per FMG level                     */
+  int32_t policy;     /* mg_policy                                          */
+  int32_t min_storage_bits; /* 0, 8, 16 or 32: smallest storage for any block;
+                         otherwise the narrowest type holding the width   */
+  int32_t w_check[MG_MAX_LEVELS + 1];
+  int32_t w_work[MG_MAX_LEVELS + 1];
+  int32_t w_inner[MG_MAX_LEVELS + 1];
+  bfp_scalar c1, c2;  /* relaxation y = c2 A r + c1 r for the stored A       */
+  bfp_scalar c1_gamma;/* c1 of D^-1 A, used in the V-residual estimate       */
+} mg_params;
+
+/* Fill *out with a complete schedule for -Laplace u = f on levels 1..L:
+ *   progressive = 0: every width (check, work, inner) equals w;
+ *   progressive = 1: check 32, working w_j = min(32, 2j + 8) and inner
+ *     w_j = min(working, max(5, w - (L - j))) (widths grow linearly with the
+ *     level, eq. width-bounds of Section 5, with m = 1 for Poisson; w is the
+ *     finest inner width);
+ * and Chebyshev coefficients for rho = 2 (an upper bound of the spectrum of
+ * D^-1 A on every level) and eta = eta_percent / 100, rescaled to the stored
+ * operator (diag 1 in 2D, 3/4 in 3D) and floor-quantized to 16 bits.      */
+int mg_params_init(int ndim, int L, int w, int progressive, int nu1, int nu2, int N,
+                   int policy, int eta_percent, mg_params* out);
+
+typedef struct mg_hierarchy mg_hierarchy;
+
+/* Device bytes a hierarchy needs in its arena.                            */
+size_t mg_hierarchy_bytes(const mg_params* prm);
+
+/* Carve a hierarchy out of a caller-provided device arena (at least
+ * mg_hierarchy_bytes, 256-byte aligned) and zero it on `stream`. The
+ * hierarchy object itself lives in host memory; destroy it with
+ * mg_hierarchy_destroy (the arena stays the caller's).                    */
+int mg_hierarchy_create(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
+                        mg_hierarchy** out);
+int mg_hierarchy_destroy(mg_hierarchy* h);
+
+/* b_j = quant(f_j / s_j) at w_check[j]: f_dev holds FP64 samples of f on the
+ * padded level-j grid (dense (n_j+2)^ndim); s_j = 4/h^2 in 2D, 8/h^2 in 3D
+ * (the scaling of setup S; a power of two, applied exactly).            */
+int mg_set_rhs(mg_hierarchy* h, int level, const double* f_dev, void* stream);
+
+/* x_level = quant(x0) at w_work[level] (an initial guess for mg_ir).     */
+int mg_set_x(mg_hierarchy* h, int level, const double* x0_dev, void* stream);
+
+/* FMG (Appendix C): x_1 = 0, then per level l = 1..L: x_l = P x_(l-1) (l>1)
+ * and N IR-V(nu1,nu2) iterations. Result in the level-L iterate.          */
+int mg_fmg(mg_hierarchy* h, void* stream);
+
+/* `iters` IR-V(nu1,nu2) iterations on level `level` from its current x.   */
+int mg_ir(mg_hierarchy* h, int level, int iters, void* stream);
+
+/* y = V(r) on `level` (r, y on the level-`level` grid at w_inner[level]).  */
+int mg_vcycle(mg_hierarchy* h, int level, const bfp_vec* r, bfp_vec* y, void* stream);
+
+/* Views of the hierarchy's blocks (device pointers into the arena).
+ * which: 0 = x (iterate), 1 = b (right-hand side), 2 = r (last IR residual). */
+int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out);
+
+/* Per-level algorithmic byte counts of everything enqueued so far, and
+ * the number of kernel launches (host-side counters).                     */
+int mg_counters(const mg_hierarchy* h, double* bytes, int64_t* launches);
+
+/* Human-readable description of the last error on this thread.           */
+const char* bfp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFPMG_H */

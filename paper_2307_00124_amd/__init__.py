@@ -1,0 +1,361 @@
+"""BFP multigrid on MI355X: Python binding of libbfpmg.so.
+
+Thin marshalling over the C-ABI declared in include/bfpmg.h: PyTorch supplies
+device memory and the stream, every computation runs in the library's HIP
+kernels. Function names match the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import abi
+from .abi import (BFP_GAMMA_EXPLICIT, BFP_GAMMA_NORM, BFP_GAMMA_SUM, BFP_META_EXP,
+                  BFP_META_FLAGS, BFP_META_MAX, BFP_META_MIN, BFP_META_MU, BFP_META_SAT,
+                  BFP_META_SLOTS, BFP_NORMALIZE, BFP_SATURATE, BFP_STENCIL_A, BFP_STENCIL_P,
+                  BFP_STENCIL_R, MG_MAX_LEVELS, MG_POLICY_NN, MG_POLICY_NN_IR_FIRST2_Q,
+                  MG_POLICY_NN_IR_FIRST_Q, MG_POLICY_NN_IR_Q, MG_POLICY_Q, BFPError, check,
+                  lib)
+
+__all__ = [
+    "Vec", "Stencil", "scalar", "gamma_norm", "gamma_sum", "gamma_explicit", "Hierarchy",
+    "bfp_layout", "bfp_vec_init", "bfp_vec_assign", "bfp_meta_reset", "mg_params_init", "bfp_vec_from_f64", "bfp_vec_to_f64",
+    "bfp_vec_check", "bfp_stencil_apply", "bfp_residual", "bfp_axpy", "bfp_sub", "bfp_dot",
+    "bfp_normalize", "bfp_saturate_truncate", "bfp_cheby_coeffs", "BFPError",
+    "BFP_NORMALIZE", "BFP_SATURATE", "BFP_STENCIL_A", "BFP_STENCIL_R", "BFP_STENCIL_P",
+    "MG_POLICY_Q", "MG_POLICY_NN", "MG_POLICY_NN_IR_FIRST_Q", "MG_POLICY_NN_IR_FIRST2_Q",
+    "MG_POLICY_NN_IR_Q", "lib",
+]
+
+_DTYPES = {8: torch.int8, 16: torch.int16, 32: torch.int32}
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def storage_for(w: int) -> int:
+    return 8 if w <= 8 else 16 if w <= 16 else 32
+
+
+def bfp_layout(ndim: int, n: int, storage_bits: int) -> tuple[int, int]:
+    pitch = C.c_int64()
+    nbytes = C.c_size_t()
+    check(lib.bfp_layout(ndim, n, storage_bits, C.byref(pitch), C.byref(nbytes)), "bfp_layout")
+    return pitch.value, nbytes.value
+
+
+class Vec:
+    """A BFP block (one exponent, w-bit mantissas) on a padded grid in device
+    memory: a byte buffer of row-pitched mantissas and 16 int64 of metadata."""
+
+    def __init__(self, ndim: int, n: int, w: int, storage_bits: int | None = None,
+                 device: str | torch.device = "cuda", init: bool = True, _view=None):
+        if _view is not None:
+            self.c, self._owner = _view
+            self.buf = None
+            self.meta = None
+            return
+        bits = storage_bits or storage_for(w)
+        pitch, nbytes = bfp_layout(ndim, n, bits)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.meta = torch.empty(BFP_META_SLOTS, dtype=torch.int64, device=device)
+        self.c = abi.bfp_vec(self.buf.data_ptr(), self.meta.data_ptr(), w, bits, ndim, n, pitch)
+        self._owner = None
+        if init:
+            bfp_vec_init(self)
+
+    @classmethod
+    def view(cls, c_vec: abi.bfp_vec, owner) -> "Vec":
+        return cls(0, 0, 0, _view=(c_vec, owner))
+
+    @property
+    def ndim(self) -> int:
+        return self.c.ndim
+
+    @property
+    def n(self) -> int:
+        return self.c.n
+
+    @property
+    def w(self) -> int:
+        return self.c.w
+
+    @property
+    def storage_bits(self) -> int:
+        return self.c.storage_bits
+
+    def _raw(self) -> torch.Tensor:
+        """The mantissa buffer as a typed device tensor (rows x pitch)."""
+        rows = (self.n + 2) ** (self.ndim - 1)
+        nbytes = rows * self.c.pitch * self.storage_bits // 8
+        if self.buf is not None:
+            b = self.buf
+        else:
+            b = _wrap_device_bytes(self.c.mant, nbytes, self._owner)
+        return b[:nbytes].view(_DTYPES[self.storage_bits]).view(rows, self.c.pitch)
+
+    def mantissas(self) -> torch.Tensor:
+        """Device view of the (n+2)^ndim mantissas (ring included)."""
+        side = self.n + 2
+        return self._raw()[:, :side].reshape((side,) * self.ndim)
+
+    def padding(self) -> torch.Tensor:
+        return self._raw()[:, self.n + 2:]
+
+    def meta_tensor(self) -> torch.Tensor:
+        if self.meta is not None:
+            return self.meta
+        return _wrap_device_bytes(self.c.meta, BFP_META_SLOTS * 8, self._owner).view(torch.int64)
+
+    def host_meta(self) -> list[int]:
+        return [int(v) for v in self.meta_tensor().cpu().tolist()]
+
+    @property
+    def exp(self) -> int:
+        return self.host_meta()[BFP_META_EXP]
+
+
+def _wrap_device_bytes(ptr: int, nbytes: int, owner) -> torch.Tensor:
+    """A uint8 tensor aliasing device memory inside a torch-owned arena."""
+    arena: torch.Tensor = owner.arena
+    base = arena.data_ptr()
+    off = int(ptr) - base
+    if off < 0 or off + nbytes > arena.numel():
+        raise ValueError("pointer outside the owning arena")
+    return arena[off:off + nbytes]
+
+
+@dataclass
+class Stencil:
+    """Constant-coefficient BFP matrix: exponent and 3^ndim integer taps
+    (index ((oz+1)*3 + (oy+1))*3 + (ox+1), 2D: (oy+1)*3 + (ox+1))."""
+    ndim: int
+    kind: int
+    exp: int
+    taps: list
+    w: int = 0
+
+    def c(self) -> abi.bfp_stencil:
+        s = abi.bfp_stencil()
+        s.ndim, s.kind, s.exp = self.ndim, self.kind, self.exp
+        width = self.w or max((abs(t) * 2).bit_length() for t in self.taps)
+        s.w = width
+        for i, t in enumerate(self.taps):
+            s.taps[i] = int(t)
+        return s
+
+
+def scalar(m: int, e: int, w: int | None = None) -> abi.bfp_scalar:
+    if w is None:
+        w = ((m if m >= 0 else ~m).bit_length()) + 1
+    return abi.bfp_scalar(m, e, w)
+
+
+def gamma_norm(a: Vec, c: abi.bfp_scalar | None = None) -> abi.bfp_gamma:
+    g = abi.bfp_gamma()
+    g.rule = BFP_GAMMA_NORM
+    g.a_meta = a.c.meta
+    g.c = c if c is not None else scalar(1, 0)
+    return g
+
+
+def gamma_sum(a: Vec, b: Vec) -> abi.bfp_gamma:
+    g = abi.bfp_gamma()
+    g.rule = BFP_GAMMA_SUM
+    g.a_meta = a.c.meta
+    g.b_meta = b.c.meta
+    return g
+
+
+def gamma_explicit(m: int, e: int) -> abi.bfp_gamma:
+    g = abi.bfp_gamma()
+    g.rule = BFP_GAMMA_EXPLICIT
+    g.c = scalar(m, e)
+    return g
+
+
+def _opt(x):
+    return C.byref(x) if x is not None else None
+
+
+def _vc(v: Vec | None):
+    return C.byref(v.c) if v is not None else None
+
+
+# ------------------------------------------------------------ C entry points --
+
+def bfp_vec_init(v: Vec, stream=None) -> None:
+    check(lib.bfp_vec_init(C.byref(v.c), _stream(stream)), "bfp_vec_init")
+
+
+def bfp_vec_assign(v: Vec, exp: int, stream=None) -> None:
+    check(lib.bfp_vec_assign(C.byref(v.c), int(exp), _stream(stream)), "bfp_vec_assign")
+
+
+def bfp_meta_reset(meta: torch.Tensor, stream=None) -> None:
+    check(lib.bfp_meta_reset(_ptr(meta), _stream(stream)), "bfp_meta_reset")
+
+
+def bfp_vec_from_f64(src: torch.Tensor, log2_scale: int, dst: Vec, stream=None) -> None:
+    if src.dtype != torch.float64 or not src.is_cuda or not src.is_contiguous():
+        raise ValueError("src must be a contiguous float64 device tensor")
+    if src.numel() != (dst.n + 2) ** dst.ndim:
+        raise ValueError("src must hold (n+2)^ndim values")
+    check(lib.bfp_vec_from_f64(_ptr(src), int(log2_scale), C.byref(dst.c), _stream(stream)),
+          "bfp_vec_from_f64")
+
+
+def bfp_vec_to_f64(src: Vec, dst: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if dst is None:
+        dst = torch.empty((src.n + 2,) * src.ndim, dtype=torch.float64, device="cuda")
+    if dst.dtype != torch.float64 or not dst.is_contiguous() or dst.numel() != (src.n + 2) ** src.ndim:
+        raise ValueError("dst must be a contiguous float64 tensor of (n+2)^ndim")
+    check(lib.bfp_vec_to_f64(C.byref(src.c), _ptr(dst), _stream(stream)), "bfp_vec_to_f64")
+    return dst
+
+
+def bfp_vec_check(v: Vec, stream=None) -> None:
+    check(lib.bfp_vec_check(C.byref(v.c), _stream(stream)), "bfp_vec_check")
+
+
+def bfp_stencil_apply(A: Stencil, x: Vec, alpha, beta, y: Vec | None, w_out: int, mode: int,
+                      gamma, z: Vec, stream=None) -> None:
+    Ac = A.c()
+    check(lib.bfp_stencil_apply(C.byref(Ac), C.byref(x.c), _opt(alpha), _opt(beta), _vc(y),
+                                w_out, mode, _opt(gamma), C.byref(z.c), _stream(stream)),
+          "bfp_stencil_apply")
+
+
+def bfp_residual(A: Stencil, x: Vec, b: Vec, w_out: int, mode: int, gamma, r: Vec,
+                 stream=None) -> None:
+    Ac = A.c()
+    check(lib.bfp_residual(C.byref(Ac), C.byref(x.c), C.byref(b.c), w_out, mode, _opt(gamma),
+                           C.byref(r.c), _stream(stream)), "bfp_residual")
+
+
+def bfp_axpy(alpha, x: Vec, beta, y: Vec, w_out: int, mode: int, gamma, z: Vec,
+             stream=None) -> None:
+    check(lib.bfp_axpy(C.byref(alpha), C.byref(x.c), C.byref(beta), C.byref(y.c), w_out, mode,
+                       _opt(gamma), C.byref(z.c), _stream(stream)), "bfp_axpy")
+
+
+def bfp_sub(x: Vec, y: Vec, w_out: int, mode: int, gamma, z: Vec, stream=None) -> None:
+    check(lib.bfp_sub(C.byref(x.c), C.byref(y.c), w_out, mode, _opt(gamma), C.byref(z.c),
+                      _stream(stream)), "bfp_sub")
+
+
+def bfp_dot(x: Vec, y: Vec, out: torch.Tensor, stream=None) -> None:
+    if out.dtype != torch.int64 or out.numel() < 8:
+        raise ValueError("out must be an int64 device tensor of 8 zero-initialised slots")
+    check(lib.bfp_dot(C.byref(x.c), C.byref(y.c), _ptr(out), _stream(stream)), "bfp_dot")
+
+
+def bfp_normalize(x: Vec, w_out: int, out: Vec, stream=None) -> None:
+    check(lib.bfp_normalize(C.byref(x.c), w_out, C.byref(out.c), _stream(stream)),
+          "bfp_normalize")
+
+
+def bfp_saturate_truncate(x: Vec, w_out: int, gamma, out: Vec, stream=None) -> None:
+    check(lib.bfp_saturate_truncate(C.byref(x.c), w_out, _opt(gamma), C.byref(out.c),
+                                    _stream(stream)), "bfp_saturate_truncate")
+
+
+def bfp_cheby_coeffs(rho: tuple[int, int], eta: tuple[int, int], scale: tuple[int, int] = (1, 1),
+                     w: int = 16) -> tuple[abi.bfp_scalar, abi.bfp_scalar]:
+    c1, c2 = abi.bfp_scalar(), abi.bfp_scalar()
+    check(lib.bfp_cheby_coeffs(rho[0], rho[1], eta[0], eta[1], scale[0], scale[1], w,
+                               C.byref(c1), C.byref(c2)), "bfp_cheby_coeffs")
+    return c1, c2
+
+
+# ------------------------------------------------------------ multigrid ---
+
+class Hierarchy:
+    """A solver hierarchy in a torch-allocated device arena (mg_* calls)."""
+
+    def __init__(self, params: abi.mg_params, device="cuda", stream=None):
+        self.params = params
+        nbytes = lib.mg_hierarchy_bytes(C.byref(params))
+        if nbytes == 0:
+            raise BFPError(abi.BFP_EINVAL, "mg_hierarchy_bytes")
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        self.arena = self.arena[off:off + nbytes]
+        h = C.c_void_p()
+        check(lib.mg_hierarchy_create(C.byref(params), _ptr(self.arena), nbytes, _stream(stream),
+                                      C.byref(h)), "mg_hierarchy_create")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.mg_hierarchy_destroy(h)
+            self.h = None
+
+    def set_rhs(self, level: int, f: torch.Tensor, stream=None) -> None:
+        if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous():
+            raise ValueError("f must be a contiguous float64 device tensor")
+        check(lib.mg_set_rhs(self.h, level, _ptr(f), _stream(stream)), "mg_set_rhs")
+
+    def set_x(self, level: int, x0: torch.Tensor, stream=None) -> None:
+        check(lib.mg_set_x(self.h, level, _ptr(x0), _stream(stream)), "mg_set_x")
+
+    def fmg(self, stream=None) -> None:
+        check(lib.mg_fmg(self.h, _stream(stream)), "mg_fmg")
+
+    def ir(self, level: int, iters: int, stream=None) -> None:
+        check(lib.mg_ir(self.h, level, iters, _stream(stream)), "mg_ir")
+
+    def vcycle(self, level: int, r: Vec, stream=None) -> Vec:
+        y = abi.bfp_vec()
+        check(lib.mg_vcycle(self.h, level, C.byref(r.c), C.byref(y), _stream(stream)),
+              "mg_vcycle")
+        return Vec.view(y, self)
+
+    def get_vec(self, level: int, which: int = 0) -> Vec:
+        v = abi.bfp_vec()
+        check(lib.mg_get_vec(self.h, level, which, C.byref(v)), "mg_get_vec")
+        return Vec.view(v, self)
+
+    def counters(self) -> tuple[float, int]:
+        b = C.c_double()
+        n = C.c_int64()
+        check(lib.mg_counters(self.h, C.byref(b), C.byref(n)), "mg_counters")
+        return b.value, n.value
+
+
+def mg_params_init(ndim: int, L: int, w: int, progressive: bool = True, nu1: int = 1,
+                   nu2: int = 0, N: int = 2, policy: int = MG_POLICY_NN_IR_FIRST_Q,
+                   eta_percent: int = 23, min_storage_bits: int = 0) -> abi.mg_params:
+    p = abi.mg_params()
+    check(lib.mg_params_init(ndim, L, w, int(progressive), nu1, nu2, N, policy, eta_percent,
+                             C.byref(p)), "mg_params_init")
+    p.min_storage_bits = min_storage_bits
+    return p
+
+
+def make_params(ndim: int, L: int, w_check: dict, w_work: dict, w_inner: dict,
+                c1: abi.bfp_scalar, c2: abi.bfp_scalar, c1_gamma: abi.bfp_scalar,
+                nu1: int = 1, nu2: int = 0, N: int = 2, policy: int = MG_POLICY_NN_IR_FIRST_Q,
+                min_storage_bits: int = 0) -> abi.mg_params:
+    p = abi.mg_params()
+    p.ndim, p.L, p.nu1, p.nu2, p.N, p.policy = ndim, L, nu1, nu2, N, policy
+    p.min_storage_bits = min_storage_bits
+    for j in range(1, L + 1):
+        p.w_check[j] = w_check[j]
+        p.w_work[j] = w_work[j]
+        p.w_inner[j] = w_inner[j]
+    p.c1, p.c2, p.c1_gamma = c1, c2, c1_gamma
+    return p

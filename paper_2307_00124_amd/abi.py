@@ -1,0 +1,122 @@
+"""ctypes mirror of include/bfpmg.h and the loader of libbfpmg.so.
+
+The library is required: importing this module raises if the shared object
+is missing (build it with ``python paper_2307_00124_amd/build.py``). There is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbfpmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bfpmg.h")
+
+BFP_OK, BFP_EINVAL, BFP_EWIDTH, BFP_ESHAPE, BFP_ENONFINITE = 0, -1, -2, -3, -4
+BFP_ENOMEM, BFP_EHIP, BFP_EBUSY, BFP_ENOTFOUND, BFP_PENDING = -5, -6, -7, -8, 1
+BFP_NORMALIZE, BFP_SATURATE = 0, 1
+BFP_STENCIL_A, BFP_STENCIL_R, BFP_STENCIL_P = 0, 1, 2
+BFP_GAMMA_NORM, BFP_GAMMA_SUM, BFP_GAMMA_EXPLICIT = 1, 2, 3
+BFP_META_SLOTS = 16
+BFP_META_EXP, BFP_META_MAX, BFP_META_MIN, BFP_META_SAT, BFP_META_MU, BFP_META_FLAGS = range(6)
+MG_POLICY_Q, MG_POLICY_NN, MG_POLICY_NN_IR_FIRST_Q, MG_POLICY_NN_IR_FIRST2_Q, MG_POLICY_NN_IR_Q = range(5)
+MG_MAX_LEVELS = 16
+
+
+class bfp_vec(C.Structure):
+    _fields_ = [("mant", C.c_void_p), ("meta", C.c_void_p), ("w", C.c_int32),
+                ("storage_bits", C.c_int32), ("ndim", C.c_int32), ("n", C.c_int32),
+                ("pitch", C.c_int64)]
+
+
+class bfp_scalar(C.Structure):
+    _fields_ = [("m", C.c_int64), ("exp", C.c_int64), ("w", C.c_int32)]
+
+
+class bfp_stencil(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("kind", C.c_int32), ("exp", C.c_int64),
+                ("w", C.c_int32), ("taps", C.c_int32 * 27)]
+
+
+class bfp_gamma(C.Structure):
+    _fields_ = [("rule", C.c_int32), ("a_meta", C.c_void_p), ("b_meta", C.c_void_p),
+                ("c", bfp_scalar)]
+
+
+_W = C.c_int32 * (MG_MAX_LEVELS + 1)
+
+
+class mg_params(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("L", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("N", C.c_int32), ("policy", C.c_int32), ("min_storage_bits", C.c_int32),
+                ("w_check", _W), ("w_work", _W), ("w_inner", _W),
+                ("c1", bfp_scalar), ("c2", bfp_scalar), ("c1_gamma", bfp_scalar)]
+
+
+P = C.POINTER
+VP = C.c_void_p
+I = C.c_int
+I64 = C.c_int64
+
+# name -> (restype, argtypes); the exported C-ABI
+SIGNATURES = {
+    "bfp_layout": (I, [I, I, I, P(I64), P(C.c_size_t)]),
+    "bfp_vec_init": (I, [P(bfp_vec), VP]),
+    "bfp_meta_reset": (I, [VP, VP]),
+    "bfp_vec_assign": (I, [P(bfp_vec), I64, VP]),
+    "bfp_vec_from_f64": (I, [VP, I64, P(bfp_vec), VP]),
+    "bfp_vec_to_f64": (I, [P(bfp_vec), VP, VP]),
+    "bfp_vec_check": (I, [P(bfp_vec), VP]),
+    "bfp_stencil_apply": (I, [P(bfp_stencil), P(bfp_vec), P(bfp_scalar), P(bfp_scalar),
+                              P(bfp_vec), I, I, P(bfp_gamma), P(bfp_vec), VP]),
+    "bfp_residual": (I, [P(bfp_stencil), P(bfp_vec), P(bfp_vec), I, I, P(bfp_gamma),
+                         P(bfp_vec), VP]),
+    "bfp_axpy": (I, [P(bfp_scalar), P(bfp_vec), P(bfp_scalar), P(bfp_vec), I, I,
+                     P(bfp_gamma), P(bfp_vec), VP]),
+    "bfp_sub": (I, [P(bfp_vec), P(bfp_vec), I, I, P(bfp_gamma), P(bfp_vec), VP]),
+    "bfp_dot": (I, [P(bfp_vec), P(bfp_vec), VP, VP]),
+    "bfp_normalize": (I, [P(bfp_vec), I, P(bfp_vec), VP]),
+    "bfp_saturate_truncate": (I, [P(bfp_vec), I, P(bfp_gamma), P(bfp_vec), VP]),
+    "bfp_cheby_coeffs": (I, [I64, I64, I64, I64, I64, I64, I, P(bfp_scalar), P(bfp_scalar)]),
+    "mg_params_init": (I, [I, I, I, I, I, I, I, I, I, P(mg_params)]),
+    "mg_hierarchy_bytes": (C.c_size_t, [P(mg_params)]),
+    "mg_hierarchy_create": (I, [P(mg_params), VP, C.c_size_t, VP, P(VP)]),
+    "mg_hierarchy_destroy": (I, [VP]),
+    "mg_set_rhs": (I, [VP, I, VP, VP]),
+    "mg_set_x": (I, [VP, I, VP, VP]),
+    "mg_fmg": (I, [VP, VP]),
+    "mg_ir": (I, [VP, I, I, VP]),
+    "mg_vcycle": (I, [VP, I, P(bfp_vec), P(bfp_vec), VP]),
+    "mg_get_vec": (I, [VP, I, I, P(bfp_vec)]),
+    "mg_counters": (I, [VP, P(C.c_double), P(I64)]),
+    "bfp_last_error": (C.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python paper_2307_00124_amd/build.py` (there is no fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load()
+
+
+class BFPError(RuntimeError):
+    def __init__(self, code: int, fn: str):
+        msg = lib.bfp_last_error().decode()
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+def check(rc: int, fn: str) -> int:
+    if rc < 0:
+        raise BFPError(rc, fn)
+    return rc

@@ -1,0 +1,445 @@
+// C-ABI entry points of the BFP library: argument validation, the integer
+// budget checks that keep every exact intermediate inside 62 bits, and the
+// dispatch of each operation onto its kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/bfpmg.h"
+#include "api_internal.hpp"
+#include "kernels.hpp"
+
+namespace bfpk {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return BFP_OK;
+  return fail(BFP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t pitch_for(int64_t n, int bits) {
+  const int64_t per16 = 128 / bits;  // elements per 16 bytes
+  return ((n + 2 + per16 - 1) / per16) * per16;
+}
+
+int64_t rows_for(int ndim, int64_t n) { return ndim == 3 ? (n + 2) * (n + 2) : (n + 2); }
+
+int check_vec(const bfp_vec* v, const char* name) {
+  if (!v) return fail(BFP_EINVAL, "%s is NULL", name);
+  if (!v->mant || !v->meta) return fail(BFP_EINVAL, "%s has a NULL pointer", name);
+  if (v->storage_bits != 8 && v->storage_bits != 16 && v->storage_bits != 32)
+    return fail(BFP_EWIDTH, "%s: storage_bits must be 8, 16 or 32", name);
+  if (v->w < 1 || v->w > v->storage_bits)
+    return fail(BFP_EWIDTH, "%s: width %d outside 1..%d", name, v->w, v->storage_bits);
+  if (v->ndim != 2 && v->ndim != 3) return fail(BFP_ESHAPE, "%s: ndim must be 2 or 3", name);
+  if (v->n < 1) return fail(BFP_ESHAPE, "%s: n must be >= 1", name);
+  const int64_t per16 = 128 / v->storage_bits;
+  if (v->pitch < v->n + 2 || v->pitch % per16)
+    return fail(BFP_ESHAPE, "%s: pitch %lld is not a multiple of %lld that holds n+2", name,
+                (long long)v->pitch, (long long)per16);
+  if ((uintptr_t)v->mant % 16) return fail(BFP_EINVAL, "%s: mantissas not 16-byte aligned", name);
+  if ((uintptr_t)v->meta % 8) return fail(BFP_EINVAL, "%s: meta not 8-byte aligned", name);
+  return BFP_OK;
+}
+
+static int check_scalar(const bfp_scalar* s, const char* name, int max_bits) {
+  if (!s) return fail(BFP_EINVAL, "%s is NULL", name);
+  const int64_t lim = (int64_t)1 << (max_bits - 1);
+  if (s->m < -lim || s->m >= lim)
+    return fail(BFP_EWIDTH, "%s: mantissa outside %d bits", name, max_bits);
+  if (s->exp < -(1ll << 40) || s->exp > (1ll << 40))
+    return fail(BFP_EINVAL, "%s: exponent out of range", name);
+  return BFP_OK;
+}
+
+int fill_gamma(const bfp_gamma* g, int mode, GammaArgs* out) {
+  std::memset(out, 0, sizeof *out);
+  if (mode != BFP_SATURATE) return BFP_OK;
+  if (!g) return fail(BFP_EINVAL, "BFP_SATURATE needs a gamma estimate");
+  out->rule = g->rule;
+  out->a = g->a_meta;
+  out->b = g->b_meta;
+  out->cm = g->c.m;
+  out->ce = g->c.exp;
+  switch (g->rule) {
+    case BFP_GAMMA_NORM:
+      if (!g->a_meta) return fail(BFP_EINVAL, "gamma NORM needs a_meta");
+      if (g->c.m <= 0 || g->c.m >= (1ll << 24)) return fail(BFP_EINVAL, "gamma NORM needs 0 < c.m < 2^24");
+      break;
+    case BFP_GAMMA_SUM:
+      if (!g->a_meta || !g->b_meta) return fail(BFP_EINVAL, "gamma SUM needs a_meta and b_meta");
+      break;
+    case BFP_GAMMA_EXPLICIT:
+      if (g->c.m < 0) return fail(BFP_EINVAL, "gamma EXPLICIT needs c >= 0");
+      break;
+    default:
+      return fail(BFP_EINVAL, "unknown gamma rule %d", g->rule);
+  }
+  if (g->c.exp < -(1ll << 40) || g->c.exp > (1ll << 40))
+    return fail(BFP_EINVAL, "gamma exponent out of range");
+  return BFP_OK;
+}
+
+static bool is_star(const bfp_stencil* A) {
+  for (int i = 0; i < (A->ndim == 3 ? 27 : 9); ++i) {
+    int o[3];
+    if (A->ndim == 3) { o[0] = i / 9 - 1; o[1] = (i / 3) % 3 - 1; o[2] = i % 3 - 1; }
+    else { o[0] = 0; o[1] = i / 3 - 1; o[2] = i % 3 - 1; }
+    const int l1 = std::abs(o[0]) + std::abs(o[1]) + std::abs(o[2]);
+    if (l1 > 1 && A->taps[i] != 0) return false;
+  }
+  return true;
+}
+
+static int tap(const bfp_stencil* A, int oz, int oy, int ox) {
+  return A->ndim == 3 ? A->taps[((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1)]
+                      : A->taps[(oy + 1) * 3 + (ox + 1)];
+}
+
+// |alpha| * sum |t| * 2^(w-1) < 2^61 and |beta| 2^(wy-1) < 2^61
+static int check_budget(const bfp_stencil* A, const bfp_vec* x, int64_t alpha_m,
+                        const bfp_vec* y, int64_t beta_m, bool* wide) {
+  long double gb = 0;
+  if (A) {
+    for (int i = 0; i < (A->ndim == 3 ? 27 : 9); ++i) gb += std::abs((long double)A->taps[i]);
+  } else {
+    gb = 1;
+  }
+  gb *= ldexpl(1.0L, x->w - 1);
+  if (wide) *wide = !(gb < ldexpl(1.0L, 31));
+  if (std::abs((long double)alpha_m) * gb >= ldexpl(1.0L, 61))
+    return fail(BFP_EWIDTH, "alpha * A x may exceed the 61-bit exact budget");
+  if (y && std::abs((long double)beta_m) * ldexpl(1.0L, y->w - 1) >= ldexpl(1.0L, 61))
+    return fail(BFP_EWIDTH, "beta * y may exceed the 61-bit exact budget");
+  return BFP_OK;
+}
+
+static void fill_common(OpArgs* op, int w_out, const bfp_vec* x, const bfp_vec* y,
+                        const bfp_vec* z) {
+  op->w_out = w_out;
+  op->x_meta = x->meta;
+  op->y_meta = y ? y->meta : x->meta;
+  op->z_meta = z->meta;
+  op->has_y = y != nullptr;
+  op->lo = -((int64_t)1 << (w_out - 1));
+  op->hi = ((int64_t)1 << (w_out - 1)) - 1;
+}
+
+// Run one op in the requested mode: nnqcomp in one launch, qcomp as the
+// mu* pass followed by the output pass.
+template <typename L, typename F>
+static int run_modes(L& launch, int mode, F&& go) {
+  if (mode == BFP_SATURATE) {
+    launch.op.mode = kModeSat;
+    return hip_check(go(launch), "kernel launch");
+  }
+  launch.op.mode = kModeQ1;
+  int rc = hip_check(go(launch), "kernel launch (qcomp pass 1)");
+  if (rc) return rc;
+  launch.op.mode = kModeQ2;
+  return hip_check(go(launch), "kernel launch (qcomp pass 2)");
+}
+
+int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar* alpha,
+                       const bfp_scalar* beta, const bfp_vec* y, int w_out, int mode,
+                       const bfp_gamma* gamma, bfp_vec* z, hipStream_t s, int rows) {
+  int rc;
+  if (!A) return fail(BFP_EINVAL, "stencil is NULL");
+  if ((rc = check_vec(x, "x")) || (rc = check_vec(z, "z"))) return rc;
+  if (y && (rc = check_vec(y, "y"))) return rc;
+  if (mode != BFP_NORMALIZE && mode != BFP_SATURATE) return fail(BFP_EINVAL, "bad mode %d", mode);
+  if (w_out < 1 || w_out > z->storage_bits)
+    return fail(BFP_EWIDTH, "w_out %d outside 1..%d", w_out, z->storage_bits);
+  if (A->ndim != x->ndim || x->ndim != z->ndim || (y && y->ndim != z->ndim))
+    return fail(BFP_ESHAPE, "dimension mismatch");
+  if (y && y->n != z->n) return fail(BFP_ESHAPE, "y and z differ in size");
+  if (x->mant == z->mant || x->meta == z->meta)
+    return fail(BFP_EINVAL, "the output of a stencil may not alias its input");
+  for (int i = 0; i < 27; ++i)
+    if (A->taps[i] < -(1 << 23) || A->taps[i] >= (1 << 23))
+      return fail(BFP_EWIDTH, "stencil taps must fit 24 bits");
+  if (A->exp < -(1ll << 40) || A->exp > (1ll << 40)) return fail(BFP_EINVAL, "stencil exponent out of range");
+  bfp_scalar one{1, 0, 2};
+  const bfp_scalar* al = alpha ? alpha : &one;
+  const bfp_scalar* be = beta ? beta : &one;
+  if ((rc = check_scalar(al, "alpha", 32))) return rc;
+  if (y && (rc = check_scalar(be, "beta", 32))) return rc;
+  bool wide = true;
+  if ((rc = check_budget(A, x, al->m, y, be->m, &wide))) return rc;
+
+  OpArgs op{};
+  fill_common(&op, w_out, x, y, z);
+  op.e_A = A->exp;
+  op.alpha_m = al->m;
+  op.alpha_e = al->exp;
+  op.beta_m = y ? be->m : 0;
+  op.beta_e = y ? be->exp : 0;
+  if ((rc = fill_gamma(gamma, mode, &op.g))) return rc;
+
+  if (A->kind == BFP_STENCIL_A) {
+    if (x->n != z->n) return fail(BFP_ESHAPE, "A: x and z differ in size");
+    if (!is_star(A))
+      return fail(BFP_EINVAL, "same-grid stencils must be star-shaped (centre and faces)");
+    StarLaunch L{};
+    L.op = op;
+    L.x = x->mant;
+    L.y = y ? y->mant : nullptr;
+    L.z = z->mant;
+    L.ndim = x->ndim;
+    L.n = x->n;
+    L.px = x->pitch;
+    L.py = y ? y->pitch : x->pitch;
+    L.pz = z->pitch;
+    L.taps[0] = tap(A, 0, 0, 0);
+    L.taps[1] = tap(A, 0, 0, -1);
+    L.taps[2] = tap(A, 0, 0, 1);
+    L.taps[3] = tap(A, 0, -1, 0);
+    L.taps[4] = tap(A, 0, 1, 0);
+    L.taps[5] = A->ndim == 3 ? tap(A, -1, 0, 0) : 0;
+    L.taps[6] = A->ndim == 3 ? tap(A, 1, 0, 0) : 0;
+    L.xbits = x->storage_bits;
+    L.ybits = y ? y->storage_bits : 32;
+    L.zbits = z->storage_bits;
+    L.wide = wide;
+    L.rows = rows > 0 ? rows : (x->ndim == 2 ? 8 : 16);
+    return run_modes(L, mode, [&](StarLaunch& l) { return launch_star(l, s); });
+  }
+  if (A->kind == BFP_STENCIL_R || A->kind == BFP_STENCIL_P) {
+    const bfp_vec* fine = A->kind == BFP_STENCIL_R ? x : z;
+    const bfp_vec* coarse = A->kind == BFP_STENCIL_R ? z : x;
+    if (fine->n != 2 * coarse->n + 1)
+      return fail(BFP_ESHAPE, "transfer: fine n must be 2 * coarse n + 1 (%d vs %d)", fine->n,
+                  coarse->n);
+    TransferLaunch L{};
+    L.op = op;
+    L.kind = A->kind;
+    L.x = x->mant;
+    L.y = y ? y->mant : nullptr;
+    L.z = z->mant;
+    L.ndim = x->ndim;
+    L.n_in = x->n;
+    L.n_out = z->n;
+    L.px = x->pitch;
+    L.py = y ? y->pitch : z->pitch;
+    L.pz = z->pitch;
+    for (int i = 0; i < 27; ++i) L.taps[i] = A->taps[i];
+    L.xbits = x->storage_bits;
+    L.ybits = y ? y->storage_bits : 32;
+    L.zbits = z->storage_bits;
+    return run_modes(L, mode, [&](TransferLaunch& l) { return launch_transfer(l, s); });
+  }
+  return fail(BFP_EINVAL, "unknown stencil kind %d", A->kind);
+}
+
+int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta,
+               const bfp_vec* y, int w_out, int mode, const bfp_gamma* gamma, bfp_vec* z,
+               hipStream_t s, int forced_mode) {
+  int rc;
+  if ((rc = check_vec(x, "x")) || (rc = check_vec(z, "z"))) return rc;
+  if (y && (rc = check_vec(y, "y"))) return rc;
+  if (w_out < 1 || w_out > z->storage_bits)
+    return fail(BFP_EWIDTH, "w_out %d outside 1..%d", w_out, z->storage_bits);
+  if (x->ndim != z->ndim || x->n != z->n || (y && (y->ndim != z->ndim || y->n != z->n)))
+    return fail(BFP_ESHAPE, "pointwise operands differ in shape");
+  if ((rc = check_scalar(alpha, "alpha", 32))) return rc;
+  if (y && (rc = check_scalar(beta, "beta", 32))) return rc;
+  if ((rc = check_budget(nullptr, x, alpha->m, y, y ? beta->m : 0, nullptr))) return rc;
+  PointLaunch L{};
+  fill_common(&L.op, w_out, x, y, z);
+  L.op.alpha_m = alpha->m;
+  L.op.alpha_e = alpha->exp;
+  L.op.beta_m = y ? beta->m : 0;
+  L.op.beta_e = y ? beta->exp : 0;
+  L.x = x->mant;
+  L.y = y ? y->mant : nullptr;
+  L.z = z->mant;
+  L.ndim = x->ndim;
+  L.n = x->n;
+  L.px = x->pitch;
+  L.py = y ? y->pitch : x->pitch;
+  L.pz = z->pitch;
+  L.xbits = x->storage_bits;
+  L.ybits = y ? y->storage_bits : 32;
+  L.zbits = z->storage_bits;
+  if (forced_mode == kModeNormMeta || forced_mode == kModeAssign) {
+    L.op.mode = forced_mode;
+    return hip_check(launch_point(L, s), "pointwise launch");
+  }
+  if (mode != BFP_NORMALIZE && mode != BFP_SATURATE) return fail(BFP_EINVAL, "bad mode %d", mode);
+  if ((rc = fill_gamma(gamma, mode, &L.op.g))) return rc;
+  return run_modes(L, mode, [&](PointLaunch& l) { return launch_point(l, s); });
+}
+
+}  // namespace bfpk
+
+using namespace bfpk;
+
+extern "C" {
+
+const char* bfp_last_error(void) { return g_last_error.c_str(); }
+
+int bfp_layout(int ndim, int n, int storage_bits, int64_t* pitch, size_t* bytes) {
+  if (ndim != 2 && ndim != 3) return fail(BFP_ESHAPE, "ndim must be 2 or 3");
+  if (n < 1) return fail(BFP_ESHAPE, "n must be >= 1");
+  if (storage_bits != 8 && storage_bits != 16 && storage_bits != 32)
+    return fail(BFP_EWIDTH, "storage_bits must be 8, 16 or 32");
+  const int64_t p = pitch_for(n, storage_bits);
+  if (pitch) *pitch = p;
+  if (bytes) *bytes = (size_t)(p * rows_for(ndim, n) * (storage_bits / 8));
+  return BFP_OK;
+}
+
+int bfp_vec_init(const bfp_vec* v, void* stream) {
+  int rc = check_vec(v, "v");
+  if (rc) return rc;
+  const size_t bytes = (size_t)(v->pitch * rows_for(v->ndim, v->n) * (v->storage_bits / 8));
+  return hip_check(launch_init(v->mant, bytes, v->meta, 1 - v->w, (hipStream_t)stream),
+                   "bfp_vec_init");
+}
+
+int bfp_meta_reset(int64_t* meta_dev, void* stream) {
+  if (!meta_dev) return fail(BFP_EINVAL, "meta is NULL");
+  return hip_check(launch_meta_reset(meta_dev, (hipStream_t)stream), "bfp_meta_reset");
+}
+
+int bfp_vec_from_f64(const double* src_dev, int64_t log2_scale, bfp_vec* dst, void* stream) {
+  int rc = check_vec(dst, "dst");
+  if (rc) return rc;
+  if (!src_dev) return fail(BFP_EINVAL, "src is NULL");
+  if (log2_scale < -(1ll << 30) || log2_scale > (1ll << 30)) return fail(BFP_EINVAL, "log2_scale out of range");
+  ConvertLaunch L{};
+  L.src = src_dev;
+  L.mant = dst->mant;
+  L.meta = dst->meta;
+  L.ndim = dst->ndim;
+  L.n = dst->n;
+  L.pitch = dst->pitch;
+  L.bits = dst->storage_bits;
+  L.w = dst->w;
+  L.log2_scale = log2_scale;
+  return hip_check(launch_from_f64(L, (hipStream_t)stream), "bfp_vec_from_f64");
+}
+
+int bfp_vec_to_f64(const bfp_vec* src, double* dst_dev, void* stream) {
+  int rc = check_vec(src, "src");
+  if (rc) return rc;
+  if (!dst_dev) return fail(BFP_EINVAL, "dst is NULL");
+  ConvertLaunch L{};
+  L.dst = dst_dev;
+  L.mant = src->mant;
+  L.meta = src->meta;
+  L.ndim = src->ndim;
+  L.n = src->n;
+  L.pitch = src->pitch;
+  L.bits = src->storage_bits;
+  L.w = src->w;
+  return hip_check(launch_to_f64(L, (hipStream_t)stream), "bfp_vec_to_f64");
+}
+
+int bfp_vec_check(const bfp_vec* v, void* stream) {
+  int rc = check_vec(v, "v");
+  if (rc) return rc;
+  int64_t flags = 0;
+  rc = hip_check(hipMemcpyAsync(&flags, v->meta + BFP_META_FLAGS, sizeof flags,
+                                hipMemcpyDeviceToHost, (hipStream_t)stream),
+                 "bfp_vec_check copy");
+  if (rc) return rc;
+  if ((rc = hip_check(hipStreamSynchronize((hipStream_t)stream), "bfp_vec_check sync"))) return rc;
+  if (flags & 1) return fail(BFP_ENONFINITE, "non-finite FP64 input");
+  return BFP_OK;
+}
+
+int bfp_stencil_apply(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar* alpha,
+                      const bfp_scalar* beta, const bfp_vec* y, int w_out, int mode,
+                      const bfp_gamma* gamma, bfp_vec* z, void* stream) {
+  return stencil_apply_impl(A, x, alpha, beta, y, w_out, mode, gamma, z, (hipStream_t)stream, 0);
+}
+
+int bfp_residual(const bfp_stencil* A, const bfp_vec* x, const bfp_vec* b, int w_out, int mode,
+                 const bfp_gamma* gamma, bfp_vec* r, void* stream) {
+  if (!b) return fail(BFP_EINVAL, "b is NULL");
+  bfp_scalar one{1, 0, 2}, mone{-1, 0, 1};
+  return stencil_apply_impl(A, x, &one, &mone, b, w_out, mode, gamma, r, (hipStream_t)stream, 0);
+}
+
+int bfp_axpy(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta, const bfp_vec* y,
+             int w_out, int mode, const bfp_gamma* gamma, bfp_vec* z, void* stream) {
+  if (!y) return fail(BFP_EINVAL, "y is NULL");
+  return point_impl(alpha, x, beta, y, w_out, mode, gamma, z, (hipStream_t)stream, -1);
+}
+
+int bfp_sub(const bfp_vec* x, const bfp_vec* y, int w_out, int mode, const bfp_gamma* gamma,
+            bfp_vec* z, void* stream) {
+  if (!y) return fail(BFP_EINVAL, "y is NULL");
+  bfp_scalar one{1, 0, 2}, mone{-1, 0, 1};
+  return point_impl(&one, x, &mone, y, w_out, mode, gamma, z, (hipStream_t)stream, -1);
+}
+
+int bfp_normalize(const bfp_vec* in, int w_out, bfp_vec* out, void* stream) {
+  bfp_scalar one{1, 0, 2};
+  return point_impl(&one, in, nullptr, nullptr, w_out, BFP_NORMALIZE, nullptr, out,
+                    (hipStream_t)stream, kModeNormMeta);
+}
+
+int bfp_saturate_truncate(const bfp_vec* in, int w_out, const bfp_gamma* gamma, bfp_vec* out,
+                          void* stream) {
+  bfp_scalar one{1, 0, 2};
+  return point_impl(&one, in, nullptr, nullptr, w_out, BFP_SATURATE, gamma, out,
+                    (hipStream_t)stream, -1);
+}
+
+int bfp_vec_assign(bfp_vec* v, int64_t exp, void* stream) {
+  int rc = check_vec(v, "v");
+  if (rc) return rc;
+  if (exp < -(1ll << 40) || exp > (1ll << 40)) return fail(BFP_EINVAL, "exponent out of range");
+  PointLaunch L{};
+  fill_common(&L.op, v->w, v, nullptr, v);
+  L.op.alpha_m = 1;
+  L.op.assign_exp = exp;
+  L.op.mode = kModeAssign;
+  L.x = v->mant;
+  L.z = v->mant;
+  L.ndim = v->ndim;
+  L.n = v->n;
+  L.px = L.py = L.pz = v->pitch;
+  L.xbits = L.zbits = v->storage_bits;
+  L.ybits = 32;
+  return hip_check(launch_point(L, (hipStream_t)stream), "bfp_vec_assign");
+}
+
+int bfp_dot(const bfp_vec* x, const bfp_vec* y, int64_t* out_dev, void* stream) {
+  int rc;
+  if ((rc = check_vec(x, "x")) || (rc = check_vec(y, "y"))) return rc;
+  if (!out_dev) return fail(BFP_EINVAL, "out is NULL");
+  if (x->ndim != y->ndim || x->n != y->n) return fail(BFP_ESHAPE, "dot operands differ in shape");
+  DotLaunch L{};
+  L.x = x->mant;
+  L.y = y->mant;
+  L.x_meta = x->meta;
+  L.y_meta = y->meta;
+  L.out = out_dev;
+  L.ndim = x->ndim;
+  L.n = x->n;
+  L.px = x->pitch;
+  L.py = y->pitch;
+  L.xbits = x->storage_bits;
+  L.ybits = y->storage_bits;
+  return hip_check(launch_dot(L, (hipStream_t)stream), "bfp_dot");
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Constants and kernel argument blocks shared by the host launchers and the
+// HIP kernels of the BFP library.
+#pragma once
+
+#include <stdint.h>
+
+namespace bfpk {
+
+constexpr int kBlock = 256;  // threads per workgroup for every kernel
+
+// metadata slots (see include/bfpmg.h); 8.. are reduction scratch
+constexpr int kMetaExp = 0, kMetaMax = 1, kMetaMin = 2, kMetaSat = 3, kMetaMu = 4,
+              kMetaFlags = 5;
+constexpr int kMetaAccMax = 8, kMetaAccMin = 9, kMetaAccSat = 10, kMetaAccMu = 11,
+              kMetaTicket = 12;
+constexpr int kMetaSlots = 16;
+
+constexpr int kGammaNorm = 1, kGammaSum = 2, kGammaExplicit = 3;
+
+// kModeSat: nnqcomp; kModeQ1 / kModeQ2: the two passes of qcomp;
+// kModeNormMeta: qcomp of a stored block whose mu* is known from its metadata;
+// kModeAssign: keep the mantissas, set the exponent, recompute the metadata
+constexpr int kModeSat = 0, kModeQ1 = 1, kModeQ2 = 2, kModeNormMeta = 3, kModeAssign = 4;
+
+struct GammaArgs {
+  int rule;
+  const int64_t* a;
+  const int64_t* b;
+  int64_t cm, ce;
+};
+
+// One quantized BFP operation z = Q(alpha * S x + beta * y).
+struct OpArgs {
+  int mode;
+  int has_y;
+  int w_out;
+  int64_t e_A;              // exponent of the stencil (0 for pointwise ops)
+  int64_t alpha_m, alpha_e;
+  int64_t beta_m, beta_e;
+  const int64_t* x_meta;
+  const int64_t* y_meta;
+  int64_t* z_meta;
+  GammaArgs g;
+  int64_t lo, hi;           // X_w_out
+  int64_t assign_exp;       // kModeAssign only
+};
+
+// A padded, row-pitched grid: rows = (n+2)^(ndim-1) rows of `pitch` elements.
+struct Grid {
+  int64_t n;       // interior points per dimension
+  int64_t pitch;   // elements per row
+};
+
+}  // namespace bfpk

@@ -1,0 +1,277 @@
+// Device-side integer primitives shared by every BFP kernel.
+//
+// Semantics (paper Section 2): two's-complement integers, arithmetic right
+// shifts that round toward minus infinity, msb(v) = the smallest b >= 1 with
+// v in X_b = [-2^(b-1), 2^(b-1) - 1] (so msb(0) = msb(-1) = 1, msb(23) = 6).
+// Every routine here is exact; values that cannot fit the 62-bit budget are
+// reported as +-2^62, which lies outside every representable output range
+// (w_out <= 32), so a following clamp saturates them correctly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace bfpk {
+
+constexpr int64_t kSatBig = (int64_t)1 << 62;
+
+__device__ __forceinline__ int bitlen64(uint64_t v) { return v ? 64 - __clzll((long long)v) : 0; }
+
+__device__ __forceinline__ int msb64(int64_t v) {
+  return bitlen64((uint64_t)(v ^ (v >> 63))) + 1;
+}
+
+__device__ __forceinline__ int msb128(__int128 v) {
+  unsigned __int128 u = (unsigned __int128)(v ^ (v >> 127));
+  uint64_t hi = (uint64_t)(u >> 64);
+  return hi ? 64 + bitlen64(hi) + 1 : bitlen64((uint64_t)u) + 1;
+}
+
+// floor(v / 2^k) for k >= 0 (k may exceed 63).
+__device__ __forceinline__ int64_t shr_floor(int64_t v, int64_t k) {
+  return v >> (k > 63 ? 63 : (int)k);
+}
+
+// a * 2^k + c for k >= 0 with |a|, |c| < 2^61: exact when |a| 2^k < 2^62,
+// otherwise +-2^62 with the sign of a (|a 2^k + c| then exceeds 2^61).
+__device__ __forceinline__ int64_t shl_add_sat(int64_t a, int64_t k, int64_t c) {
+  if (a == 0) return c;
+  uint64_t mag = (uint64_t)(a < 0 ? -a : a);
+  if (k + bitlen64(mag) >= 63) return a > 0 ? kSatBig : -kSatBig;
+  return (int64_t)((uint64_t)a << k) + c;
+}
+
+// How floor(a 2^sa + b 2^sb) is evaluated without overflow. The term with
+// the larger shift is "hi"; D = s_hi - s_lo >= 0.
+//   kInt:       s_lo >= 0          value = (hi 2^D + lo) 2^s_lo
+//   kHighShift: s_lo < 0, D >= L   value = hi 2^(D-L) + floor(lo / 2^L)
+//   kShiftDown: s_lo < 0, D < L    value = floor((hi + floor(lo/2^D)) / 2^(L-D))
+// with L = -s_lo (the last form is exact because hi is an integer).
+enum { kInt = 0, kHighShift = 1, kShiftDown = 2 };
+
+struct Combine {
+  int kind;
+  int swap;      // 1: hi is the second operand
+  int64_t D, L, s_lo;
+};
+
+__device__ __forceinline__ Combine make_combine(int64_t sa, int64_t sb) {
+  Combine c;
+  c.swap = sa < sb;
+  int64_t s_hi = c.swap ? sb : sa;
+  int64_t s_lo = c.swap ? sa : sb;
+  c.D = s_hi - s_lo;
+  c.s_lo = s_lo;
+  c.L = -s_lo;
+  if (s_lo >= 0) c.kind = kInt;
+  else if (c.D >= c.L) c.kind = kHighShift;
+  else c.kind = kShiftDown;
+  return c;
+}
+
+// floor(a 2^sa + b 2^sb), +-2^62 when beyond range. |a|, |b| < 2^61.
+__device__ __forceinline__ int64_t combine(const Combine& c, int64_t a, int64_t b) {
+  int64_t hi = c.swap ? b : a;
+  int64_t lo = c.swap ? a : b;
+  if (c.kind == kInt) {
+    int64_t v = shl_add_sat(hi, c.D, lo);
+    return c.s_lo == 0 ? v : shl_add_sat(v, c.s_lo, 0);
+  }
+  if (c.kind == kHighShift) return shl_add_sat(hi, c.D - c.L, shr_floor(lo, c.L));
+  return shr_floor(hi + shr_floor(lo, c.D), c.L - c.D);
+}
+
+// floor(a 2^s) for a single term.
+__device__ __forceinline__ int64_t scale1(int64_t a, int64_t s) {
+  return s >= 0 ? shl_add_sat(a, s, 0) : shr_floor(a, -s);
+}
+
+// msb of the exact z* = hi 2^D + lo (D >= 0), |hi|, |lo| < 2^61.
+__device__ __forceinline__ int msb_exact2(int64_t hi, int64_t lo, int64_t D) {
+  if (D <= 64) {
+    __int128 t = (__int128)((unsigned __int128)(__int128)hi << (int)D) + (__int128)lo;
+    return msb128(t);
+  }
+  if (hi == 0) return msb64(lo);
+  // msb(floor(v / 2^k)) = msb(v) - k whenever the quotient is not 0 or -1
+  __int128 t = (__int128)((unsigned __int128)(__int128)hi << 64) + (__int128)shr_floor(lo, D - 64);
+  return msb128(t) + (int)(D - 64);
+}
+
+// ------------------------------------------------------------ estimates --
+
+// nu(gamma) = floor(log2 gamma) + 2 for the device-evaluated estimate, or
+// sets *zero when gamma = 0.
+__device__ __forceinline__ int64_t norm_mag(const int64_t* m) {
+  int64_t mx = m[kMetaMax], mn = m[kMetaMin];
+  return mx > -mn ? mx : -mn;
+}
+
+__device__ __forceinline__ int64_t gamma_nu(const GammaArgs& g, bool* zero) {
+  *zero = false;
+  if (g.rule == kGammaNorm) {
+    int64_t M = norm_mag(g.a);
+    if (M == 0) { *zero = true; return 0; }
+    uint64_t prod = (uint64_t)M * (uint64_t)g.cm;
+    return (int64_t)bitlen64(prod) + 1 + g.ce + g.a[kMetaExp];
+  }
+  if (g.rule == kGammaSum) {
+    int64_t Ma = norm_mag(g.a), Mb = norm_mag(g.b);
+    int64_t ea = g.a[kMetaExp], eb = g.b[kMetaExp];
+    if (Ma == 0 && Mb == 0) { *zero = true; return 0; }
+    if (Ma == 0) return (int64_t)bitlen64((uint64_t)Mb) + 1 + eb;
+    if (Mb == 0) return (int64_t)bitlen64((uint64_t)Ma) + 1 + ea;
+    if (ea < eb) { int64_t t = Ma; Ma = Mb; Mb = t; t = ea; ea = eb; eb = t; }
+    int64_t k = ea - eb;  // Ma carries the larger exponent
+    if (k <= 31) return (int64_t)bitlen64(((uint64_t)Ma << k) + (uint64_t)Mb) + 1 + eb;
+    // Mb <= 2^31 < 2^k: floor(log2(Ma 2^k + Mb)) = floor(log2 Ma) + k
+    return (int64_t)bitlen64((uint64_t)Ma) + 1 + ea;
+  }
+  // explicit value c >= 0
+  if (g.cm == 0) { *zero = true; return 0; }
+  return (int64_t)msb64(g.cm) + g.ce;
+}
+
+// ------------------------------------------------ metadata reductions --
+
+__device__ __forceinline__ int64_t wave_max(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) { int64_t t = __shfl_xor(v, o, 64); v = t > v ? t : v; }
+  return v;
+}
+__device__ __forceinline__ int64_t wave_min(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) { int64_t t = __shfl_xor(v, o, 64); v = t < v ? t : v; }
+  return v;
+}
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int64_t atomic_load64(const int64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store64(int64_t* p, int64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reduce the per-thread (max, min, saturations) of a block's outputs, merge
+// them into the output metadata's scratch slots, and let the last block of
+// the grid publish exponent / max / min / saturation count and reset the
+// scratch. Works for any grid size; the scratch is left ready for the next
+// launch, so no separate reset kernel is needed. Block size: kBlock.
+__device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64_t tsat,
+                                               int64_t* zm, int64_t e_out) {
+  __shared__ int64_t s_red[3][kBlock / 64];
+  __shared__ int s_last;
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x + threadIdx.z * blockDim.x * blockDim.y;
+  tmax = wave_max(tmax);
+  tmin = wave_min(tmin);
+  tsat = wave_sum(tsat);
+  if ((tid & 63) == 0) {
+    s_red[0][tid >> 6] = tmax;
+    s_red[1][tid >> 6] = tmin;
+    s_red[2][tid >> 6] = tsat;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t bmax = s_red[0][0], bmin = s_red[1][0], bsat = s_red[2][0];
+    for (int i = 1; i < kBlock / 64; ++i) {
+      bmax = s_red[0][i] > bmax ? s_red[0][i] : bmax;
+      bmin = s_red[1][i] < bmin ? s_red[1][i] : bmin;
+      bsat += s_red[2][i];
+    }
+    atomicMax((long long*)&zm[kMetaAccMax], (long long)bmax);
+    atomicMin((long long*)&zm[kMetaAccMin], (long long)bmin);
+    if (bsat) atomicAdd((unsigned long long*)&zm[kMetaAccSat], (unsigned long long)bsat);
+    __threadfence();
+    const unsigned long long nblk = (unsigned long long)gridDim.x * gridDim.y * gridDim.z;
+    unsigned long long t = atomicAdd((unsigned long long*)&zm[kMetaTicket], 1ull);
+    s_last = (t == nblk - 1);
+    if (s_last) {
+      __threadfence();
+      int64_t mx = atomic_load64(&zm[kMetaAccMax]);
+      int64_t mn = atomic_load64(&zm[kMetaAccMin]);
+      int64_t st = atomic_load64(&zm[kMetaAccSat]);
+      zm[kMetaMax] = mx;
+      zm[kMetaMin] = mn;
+      zm[kMetaSat] = st;
+      zm[kMetaExp] = e_out;
+      atomic_store64(&zm[kMetaAccMax], INT64_MIN);
+      atomic_store64(&zm[kMetaAccMin], INT64_MAX);
+      atomic_store64(&zm[kMetaAccSat], 0);
+      atomic_store64(&zm[kMetaTicket], 0);
+    }
+  }
+}
+
+// First pass of qcomp: reduce mu* = max(1, max msb(z*_i)) into the output
+// metadata; the last block stores it in kMetaMu.
+__device__ __forceinline__ void finish_mu(int64_t tmu, int64_t* zm) {
+  __shared__ int64_t s_red[kBlock / 64];
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x + threadIdx.z * blockDim.x * blockDim.y;
+  tmu = wave_max(tmu);
+  if ((tid & 63) == 0) s_red[tid >> 6] = tmu;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t b = s_red[0];
+    for (int i = 1; i < kBlock / 64; ++i) b = s_red[i] > b ? s_red[i] : b;
+    atomicMax((long long*)&zm[kMetaAccMu], (long long)b);
+    __threadfence();
+    const unsigned long long nblk = (unsigned long long)gridDim.x * gridDim.y * gridDim.z;
+    unsigned long long t = atomicAdd((unsigned long long*)&zm[kMetaTicket], 1ull);
+    if (t == nblk - 1) {
+      __threadfence();
+      int64_t mu = atomic_load64(&zm[kMetaAccMu]);
+      zm[kMetaMu] = mu < 1 ? 1 : mu;
+      atomic_store64(&zm[kMetaAccMu], 0);
+      atomic_store64(&zm[kMetaTicket], 0);
+    }
+  }
+}
+
+// --------------------------------------------------------- op planning --
+
+// Everything a kernel derives once (uniformly) from the metadata of its
+// operands: the exponents of the two exact terms a = alpha A x (exponent ea)
+// and b = beta y (exponent eb), e_z* = min(ea, eb), the output exponent and
+// the combine plan.
+struct Resolved {
+  int64_t ea, eb, ez, eo;
+  Combine cmb;
+  int64_t sa;    // single-term shift when there is no y
+};
+
+__device__ __forceinline__ Resolved resolve(const OpArgs& p) {
+  Resolved r;
+  r.ea = p.alpha_e + p.e_A + p.x_meta[kMetaExp];
+  r.eb = p.has_y ? p.beta_e + p.y_meta[kMetaExp] : r.ea;
+  r.ez = r.ea < r.eb ? r.ea : r.eb;
+  if (p.mode == kModeSat) {
+    bool zero;
+    int64_t nu = gamma_nu(p.g, &zero);
+    r.eo = zero ? r.ez + 1 - p.w_out : nu - p.w_out;
+  } else if (p.mode == kModeQ2) {
+    r.eo = r.ez + p.z_meta[kMetaMu] - p.w_out;
+  } else if (p.mode == kModeNormMeta) {
+    // mu* of a stored block from its max / min (msb is monotone in |v|)
+    int64_t a = msb64(p.x_meta[kMetaMax]), b = msb64(p.x_meta[kMetaMin]);
+    r.eo = r.ez + (a > b ? a : b) - p.w_out;
+  } else if (p.mode == kModeAssign) {
+    r.eo = p.assign_exp;
+  } else {
+    r.eo = 0;
+  }
+  r.sa = p.mode == kModeAssign ? 0 : r.ea - r.eo;
+  r.cmb = make_combine(r.ea - r.eo, r.eb - r.eo);
+  return r;
+}
+
+__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi, int64_t& sat) {
+  if (v < lo) { ++sat; return lo; }
+  if (v > hi) { ++sat; return hi; }
+  return v;
+}
+
+}  // namespace bfpk

@@ -1,0 +1,102 @@
+// The quantizing epilogue every BFP kernel applies to its exact per-point
+// result, and vector load/store helpers.
+//
+// For an exact stencil row sum g (or a stored mantissa, for pointwise ops)
+// and an optional y entry, the exact result is z* = a 2^ea + b 2^eb with
+// a = alpha_m * g and b = beta_m * y (the exact gemv / axpby rows of the
+// paper's Appendix B, with the operand of larger exponent shifted left).
+//   - first qcomp pass (kQ1): accumulate mu* = max msb(z*) (z* held exactly
+//     in 128 bits);
+//   - every other mode: write floor(z* 2^(e_z* - e_out)) clamped to X_w_out,
+//     with e_out fixed by the mode (estimate, mu*, or the input's metadata),
+//     and accumulate max / min / saturation count of the outputs.
+#pragma once
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace bfpk {
+
+constexpr int kQ1 = 1;   // template flag: first qcomp pass
+constexpr int kOut = 0;  // template flag: output-writing pass (mode chosen at run time)
+
+template <typename T>
+__device__ __forceinline__ void ld4(const T* base, int64_t off, int32_t (&v)[4], bool ok) {
+  if (ok) {
+    Q4<T> q = *reinterpret_cast<const Q4<T>*>(base + off);
+    v[0] = q.v[0]; v[1] = q.v[1]; v[2] = q.v[2]; v[3] = q.v[3];
+  } else {
+    v[0] = v[1] = v[2] = v[3] = 0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void st4(T* base, int64_t off, const int64_t (&v)[4]) {
+  Q4<T> q;
+  q.v[0] = (T)v[0]; q.v[1] = (T)v[1]; q.v[2] = (T)v[2]; q.v[3] = (T)v[3];
+  *reinterpret_cast<Q4<T>*>(base + off) = q;
+}
+
+template <int PASS, bool HASY>
+struct Epi {
+  Resolved R;
+  int64_t alpha_m, beta_m, lo, hi;
+  int64_t D;       // first pass: exponent gap of the two terms
+  int swap;        // first pass: the y term carries the larger exponent
+  int64_t tmax, tmin, tsat, tmu;
+  int64_t* zm;
+
+  __device__ __forceinline__ void init(const OpArgs& op) {
+    R = resolve(op);
+    alpha_m = op.alpha_m;
+    beta_m = op.beta_m;
+    lo = op.lo;
+    hi = op.hi;
+    zm = op.z_meta;
+    swap = R.ea < R.eb;
+    D = swap ? R.eb - R.ea : R.ea - R.eb;
+    tmax = 0;
+    tmin = 0;
+    tsat = 0;
+    tmu = 1;
+  }
+
+  // Process one interior output point; returns its mantissa (0 in pass 1).
+  __device__ __forceinline__ int64_t apply(int64_t g, int64_t yv) {
+    const int64_t a = alpha_m * g;
+    if (PASS == kQ1) {
+      int m;
+      if (HASY) {
+        const int64_t b = beta_m * yv;
+        m = swap ? msb_exact2(b, a, D) : msb_exact2(a, b, D);
+      } else {
+        m = msb64(a);
+      }
+      tmu = m > tmu ? m : tmu;
+      return 0;
+    }
+    int64_t v = HASY ? combine(R.cmb, a, beta_m * yv) : scale1(a, R.sa);
+    v = clamp64(v, lo, hi, tsat);
+    tmax = v > tmax ? v : tmax;
+    tmin = v < tmin ? v : tmin;
+    return v;
+  }
+
+  __device__ __forceinline__ void finish() {
+    if (PASS == kQ1) finish_mu(tmu, zm);
+    else finish_outputs(tmax, tmin, tsat, zm, R.eo);
+  }
+};
+
+// Storage-type dispatch helpers (host side).
+template <typename F>
+inline hipError_t with_type(int bits, F&& f) {
+  switch (bits) {
+    case 8: return f((int8_t)0);
+    case 16: return f((int16_t)0);
+    case 32: return f((int32_t)0);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace bfpk

@@ -1,0 +1,91 @@
+// Host-side launch descriptions of the BFP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace bfpk {
+
+// Vector loads / stores of four consecutive mantissas.
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+  T v[4];
+};
+
+// z = Q(alpha * A x + beta * y) for a star stencil (center + 2*ndim faces)
+// on one grid. taps: center, -x, +x, -y, +y, -z, +z.
+struct StarLaunch {
+  OpArgs op;
+  const void* x;
+  const void* y;
+  void* z;
+  int ndim;
+  int64_t n;
+  int64_t px, py, pz;
+  int32_t taps[7];
+  int xbits, ybits, zbits;
+  int wide;   // 1: accumulate the stencil sum in int64
+  int rows;   // rows (2D) or planes (3D) marched by one wave
+};
+hipError_t launch_star(const StarLaunch& L, hipStream_t s);
+
+// Restriction (fine n_f -> coarse n_c = (n_f - 1) / 2) with full 3^d taps,
+// or prolongation (coarse -> fine) with full 3^d taps on the upsampled grid.
+struct TransferLaunch {
+  OpArgs op;
+  int kind;        // 1 = R, 2 = P
+  const void* x;   // input grid (fine for R, coarse for P)
+  const void* y;   // on the output grid (may be null)
+  void* z;         // output grid
+  int ndim;
+  int64_t n_in, n_out;
+  int64_t px, py, pz;
+  int32_t taps[27];
+  int xbits, ybits, zbits;
+};
+hipError_t launch_transfer(const TransferLaunch& L, hipStream_t s);
+
+// Pointwise z = Q(alpha x + beta y) on one grid (y optional).
+struct PointLaunch {
+  OpArgs op;
+  const void* x;
+  const void* y;
+  void* z;
+  int ndim;
+  int64_t n;
+  int64_t px, py, pz;
+  int xbits, ybits, zbits;
+};
+hipError_t launch_point(const PointLaunch& L, hipStream_t s);
+
+// FP64 <-> BFP conversion, initialisation and the exact dot product.
+struct ConvertLaunch {
+  const double* src;   // dense (n+2)^ndim
+  double* dst;
+  void* mant;
+  int64_t* meta;
+  int ndim;
+  int64_t n, pitch;
+  int bits, w;
+  int64_t log2_scale;
+};
+hipError_t launch_from_f64(const ConvertLaunch& L, hipStream_t s);
+hipError_t launch_to_f64(const ConvertLaunch& L, hipStream_t s);
+hipError_t launch_init(void* mant, size_t bytes, int64_t* meta, int64_t exp, hipStream_t s);
+hipError_t launch_meta_reset(int64_t* meta, hipStream_t s);
+
+struct DotLaunch {
+  const void* x;
+  const void* y;
+  const int64_t* x_meta;
+  const int64_t* y_meta;
+  int64_t* out;
+  int ndim;
+  int64_t n, px, py;
+  int xbits, ybits;
+};
+hipError_t launch_dot(const DotLaunch& L, hipStream_t s);
+
+}  // namespace bfpk

@@ -1,0 +1,489 @@
+// BFP multigrid driver: IR, V(nu1, nu2) and FMG (paper Appendix C) built on
+// the BFP operations of the library, with the Table 1 estimates evaluated on
+// the device from the metadata of earlier results, so a whole solve is one
+// stream of kernel launches with no host synchronization.
+//
+// Operators after the setup S (each level's equations divided by s_j, a
+// power of two, so that no BFP division occurs):
+//   2D: s_j = 4/h^2      A' = [1; -1/4 x4]        = 2^-2 [4; -1]
+//                        R' = P^T                 = 2^-2 [1 2 1; 2 4 2; 1 2 1]
+//                        P  = bilinear            = 2^-2 [1 2 1; 2 4 2; 1 2 1]
+//   3D: s_j = 8/h^2      A' = [3/4; -1/8 x6]      = 2^-3 [6; -1]
+//                        R' = P^T / 2             = 2^-4 * 2^(3 - |o|_1)
+//                        P  = trilinear           = 2^-3 * 2^(3 - |o|_1)
+// (the 3D scaling is a power of two because diag(A_h) = 6/h^2 would put the
+// non-dyadic 1/6 into A'). b'_j = f_j / s_j is an exact exponent shift.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/bfpmg.h"
+#include "api_internal.hpp"
+#include "kernels.hpp"
+
+using namespace bfpk;
+
+namespace {
+
+enum Site { kIrResFirst, kIrRes, kIrCorr, kRelax, kVRes, kRestrict, kVCorr, kFmgProl };
+
+struct Level {
+  int j;
+  int64_t n;
+  bfp_vec x, b, r, vr, y, s, t;
+};
+
+}  // namespace
+
+struct mg_hierarchy {
+  mg_params prm;
+  Level lv[MG_MAX_LEVELS + 1];
+  bfp_stencil A, R, P;
+  bfp_scalar vres;      // (2 c1 + 1) / 4 with the D-scaled c1, exact
+  double bytes;
+  int64_t launches;
+};
+
+namespace {
+
+int storage_for(int w, int min_bits) {
+  int b = w <= 8 ? 8 : (w <= 16 ? 16 : 32);
+  return b < min_bits ? min_bits : b;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------ stencils --
+
+void make_stencils(int ndim, bfp_stencil* A, bfp_stencil* R, bfp_stencil* P) {
+  std::memset(A, 0, sizeof *A);
+  std::memset(R, 0, sizeof *R);
+  std::memset(P, 0, sizeof *P);
+  A->ndim = R->ndim = P->ndim = ndim;
+  A->kind = BFP_STENCIL_A;
+  R->kind = BFP_STENCIL_R;
+  P->kind = BFP_STENCIL_P;
+  const int nt = ndim == 3 ? 27 : 9;
+  for (int i = 0; i < nt; ++i) {
+    int l1;
+    if (ndim == 3) l1 = std::abs(i / 9 - 1) + std::abs((i / 3) % 3 - 1) + std::abs(i % 3 - 1);
+    else l1 = std::abs(i / 3 - 1) + std::abs(i % 3 - 1);
+    // interpolation weight 2^-l1 times the common scale
+    if (ndim == 2) {
+      A->taps[i] = l1 == 0 ? 4 : (l1 == 1 ? -1 : 0);
+      R->taps[i] = 4 >> l1;
+      P->taps[i] = 4 >> l1;
+    } else {
+      A->taps[i] = l1 == 0 ? 6 : (l1 == 1 ? -1 : 0);
+      R->taps[i] = 8 >> l1;
+      P->taps[i] = 8 >> l1;
+    }
+  }
+  if (ndim == 2) {
+    A->exp = -2; A->w = 4;
+    R->exp = -2; R->w = 4;
+    P->exp = -2; P->w = 4;
+  } else {
+    A->exp = -3; A->w = 4;
+    R->exp = -4; R->w = 5;
+    P->exp = -3; P->w = 5;
+  }
+}
+
+// ----------------------------------------------------------- estimates --
+
+bfp_gamma g_norm(const bfp_vec& a, bfp_scalar c) {
+  bfp_gamma g{};
+  g.rule = BFP_GAMMA_NORM;
+  g.a_meta = a.meta;
+  g.c = c;
+  return g;
+}
+bfp_gamma g_sum(const bfp_vec& a, const bfp_vec& b) {
+  bfp_gamma g{};
+  g.rule = BFP_GAMMA_SUM;
+  g.a_meta = a.meta;
+  g.b_meta = b.meta;
+  return g;
+}
+const bfp_scalar kOne{1, 0, 2};
+const bfp_scalar kMinusOne{-1, 0, 1};
+const bfp_scalar kFour{1, 2, 2};   // ||R'||_inf = 4 in 2D and 3D
+
+double pts(const bfp_vec& v) {
+  double n = (double)v.n;
+  return v.ndim == 3 ? n * n * n : n * n;
+}
+double sz(const bfp_vec& v) { return v.storage_bits / 8.0; }
+
+int mode_for(const mg_hierarchy* h, Site site, bool plain_first2) {
+  switch (h->prm.policy) {
+    case MG_POLICY_Q: return BFP_NORMALIZE;
+    case MG_POLICY_NN: return BFP_SATURATE;
+    case MG_POLICY_NN_IR_FIRST_Q:
+      return site == kIrResFirst ? BFP_NORMALIZE : BFP_SATURATE;
+    case MG_POLICY_NN_IR_FIRST2_Q:
+      return (site == kIrResFirst || (site == kIrRes && plain_first2)) ? BFP_NORMALIZE
+                                                                        : BFP_SATURATE;
+    case MG_POLICY_NN_IR_Q:
+      return (site == kIrResFirst || site == kIrRes) ? BFP_NORMALIZE : BFP_SATURATE;
+  }
+  return BFP_SATURATE;
+}
+
+// --------------------------------------------------------------- ops ----
+
+int op_stencil(mg_hierarchy* h, const bfp_stencil* S, const bfp_vec& x, const bfp_scalar* al,
+               const bfp_scalar* be, const bfp_vec* y, bfp_vec& z, int mode, const bfp_gamma& g,
+               hipStream_t s) {
+  int rc = stencil_apply_impl(S, &x, al, be, y, z.w, mode, &g, &z, s, 0);
+  if (rc) return rc;
+  const int passes = mode == BFP_NORMALIZE ? 2 : 1;
+  const double rd = pts(x) * sz(x) + (y ? pts(*y) * sz(*y) : 0.0);
+  h->bytes += passes * rd + pts(z) * sz(z);
+  h->launches += passes;
+  return BFP_OK;
+}
+
+int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, int mode,
+           const bfp_gamma& g, hipStream_t s) {
+  int rc = point_impl(&kOne, &x, &kMinusOne, &y, z.w, mode, &g, &z, s, -1);
+  if (rc) return rc;
+  const int passes = mode == BFP_NORMALIZE ? 2 : 1;
+  h->bytes += passes * (pts(x) * sz(x) + pts(y) * sz(y)) + pts(z) * sz(z);
+  h->launches += passes;
+  return BFP_OK;
+}
+
+// y = V(l, rin)
+int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
+  Level& L = h->lv[l];
+  const mg_params& p = h->prm;
+  int rc;
+  // relaxation from y = 0: y = c2 A r + c1 r
+  if ((rc = op_stencil(h, &h->A, rin, &p.c2, &p.c1, &rin, L.y, mode_for(h, kRelax, false),
+                       g_norm(rin, p.c1), s)))
+    return rc;
+  const bfp_vec* last = nullptr;
+  for (int k = 1; k < p.nu1; ++k) {
+    if ((rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
+                         mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
+      return rc;
+    if ((rc = op_stencil(h, &h->A, L.s, &p.c2, &p.c1, &L.s, L.t, mode_for(h, kRelax, false),
+                         g_norm(L.s, p.c1), s)))
+      return rc;
+    if ((rc = op_sub(h, L.y, L.t, L.y, mode_for(h, kVCorr, false), g_sum(L.y, L.t), s)))
+      return rc;
+    last = &L.s;
+  }
+  if (l > 1) {
+    Level& C = h->lv[l - 1];
+    if ((rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
+                         mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
+      return rc;
+    if ((rc = op_stencil(h, &h->R, L.s, &kOne, nullptr, nullptr, C.vr,
+                         mode_for(h, kRestrict, false), g_norm(L.s, kFour), s)))
+      return rc;
+    if ((rc = vcycle(h, l - 1, C.vr, s))) return rc;
+    if ((rc = op_stencil(h, &h->P, C.y, &kMinusOne, &kOne, &L.y, L.y,
+                         mode_for(h, kVCorr, false), g_sum(L.y, C.y), s)))
+      return rc;
+    last = &L.s;
+  }
+  for (int k = 0; k < p.nu2; ++k) {
+    bfp_gamma g = last ? g_norm(*last, kOne) : g_norm(rin, h->vres);
+    if ((rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
+                         mode_for(h, kVRes, false), g, s)))
+      return rc;
+    if ((rc = op_stencil(h, &h->A, L.s, &p.c2, &p.c1, &L.s, L.t, mode_for(h, kRelax, false),
+                         g_norm(L.s, p.c1), s)))
+      return rc;
+    if ((rc = op_sub(h, L.y, L.t, L.y, mode_for(h, kVCorr, false), g_sum(L.y, L.t), s)))
+      return rc;
+    last = &L.s;
+  }
+  return BFP_OK;
+}
+
+// one IR-V iteration on level l; gamma = the estimate for the residual
+int ir_iteration(mg_hierarchy* h, int l, const bfp_gamma* gres, bool first, bool plain_first2,
+                 hipStream_t s) {
+  Level& L = h->lv[l];
+  int rc;
+  int mode = mode_for(h, first ? kIrResFirst : kIrRes, plain_first2);
+  if (!gres) mode = BFP_NORMALIZE;   // no estimate exists: qcomp
+  bfp_gamma gdummy{};
+  gdummy.rule = BFP_GAMMA_EXPLICIT;
+  if ((rc = op_stencil(h, &h->A, L.x, &kOne, &kMinusOne, &L.b, L.r, mode,
+                       gres ? *gres : gdummy, s)))
+    return rc;
+  if ((rc = vcycle(h, l, L.r, s))) return rc;
+  return op_sub(h, L.x, L.y, L.x, mode_for(h, kIrCorr, false), g_sum(L.x, L.y), s);
+}
+
+int check_params(const mg_params* p) {
+  if (!p) return fail(BFP_EINVAL, "params are NULL");
+  if (p->ndim != 2 && p->ndim != 3) return fail(BFP_ESHAPE, "ndim must be 2 or 3");
+  if (p->L < 1 || p->L > MG_MAX_LEVELS) return fail(BFP_ESHAPE, "L must be in 1..%d", MG_MAX_LEVELS);
+  if (p->nu1 < 1 || p->nu2 < 0 || p->N < 1) return fail(BFP_EINVAL, "need nu1 >= 1, nu2 >= 0, N >= 1");
+  if (p->policy < MG_POLICY_Q || p->policy > MG_POLICY_NN_IR_Q) return fail(BFP_EINVAL, "bad policy");
+  if (p->min_storage_bits != 0 && p->min_storage_bits != 8 && p->min_storage_bits != 16 &&
+      p->min_storage_bits != 32)
+    return fail(BFP_EWIDTH, "min_storage_bits must be 0, 8, 16 or 32");
+  for (int j = 1; j <= p->L; ++j) {
+    if (p->w_check[j] < 1 || p->w_check[j] > 32 || p->w_work[j] < 1 || p->w_work[j] > 32 ||
+        p->w_inner[j] < 1 || p->w_inner[j] > 32)
+      return fail(BFP_EWIDTH, "level %d: widths must be in 1..32", j);
+  }
+  if (p->c1.m <= 0 || p->c2.m >= 0) return fail(BFP_EINVAL, "need c1 > 0 > c2");
+  if (p->c1.m >= (1 << 23) || p->c2.m < -(1 << 23) || p->c1_gamma.m <= 0 ||
+      p->c1_gamma.m >= (1 << 23))
+    return fail(BFP_EWIDTH, "Chebyshev coefficients must fit 24 bits");
+  return BFP_OK;
+}
+
+// Lay out (or only size) every level's blocks in the arena.
+size_t layout(mg_hierarchy* h, const mg_params* p, char* base) {
+  size_t off = 0;
+  const int mb = p->min_storage_bits;
+  for (int j = 1; j <= p->L; ++j) {
+    Level& L = h->lv[j];
+    L.j = j;
+    L.n = ((int64_t)1 << j) - 1;
+    const int w_vr = j < p->L ? p->w_inner[j + 1] : p->w_inner[j];
+    struct Spec { bfp_vec* v; int w; } specs[] = {
+        {&L.x, p->w_work[j]}, {&L.b, p->w_check[j]}, {&L.r, p->w_inner[j]},
+        {&L.vr, w_vr},        {&L.y, p->w_inner[j]}, {&L.s, p->w_inner[j]},
+        {&L.t, p->w_inner[j]}};
+    for (auto& sp : specs) {
+      bfp_vec& v = *sp.v;
+      v.w = sp.w;
+      v.storage_bits = storage_for(sp.w, mb);
+      v.ndim = p->ndim;
+      v.n = (int32_t)L.n;
+      v.pitch = pitch_for(L.n, v.storage_bits);
+      const size_t bytes = (size_t)(v.pitch * rows_for(p->ndim, L.n) * (v.storage_bits / 8));
+      v.mant = base ? base + off : nullptr;
+      off = align256(off + bytes);
+      v.meta = base ? (int64_t*)(base + off) : nullptr;
+      off = align256(off + kMetaSlots * sizeof(int64_t));
+    }
+  }
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bfp_cheby_coeffs(int64_t rho_num, int64_t rho_den, int64_t eta_num, int64_t eta_den,
+                     int64_t scale_num, int64_t scale_den, int w, bfp_scalar* c1,
+                     bfp_scalar* c2) {
+  if (!c1 || !c2) return fail(BFP_EINVAL, "outputs are NULL");
+  const int64_t lim = 1 << 12;
+  if (rho_num <= 0 || rho_den <= 0 || eta_num <= 0 || eta_den <= eta_num || scale_num <= 0 ||
+      scale_den <= 0 || rho_num > lim || rho_den > lim || eta_den > lim || scale_num > lim ||
+      scale_den > lim)
+    return fail(BFP_EINVAL, "need 0 < eta < 1, rho > 0, scale > 0 with terms up to 2^12");
+  if (w < 2 || w > 24) return fail(BFP_EWIDTH, "w must be in 2..24");
+  typedef __int128 i128;
+  // alpha = An / Ad and c = Cn / Ad share a denominator; beta = den / (2 An Ad)
+  const i128 An = (i128)(eta_den + eta_num) * rho_num, Cn = (i128)(eta_den - eta_num) * rho_num;
+  const i128 Ad = (i128)2 * eta_den * rho_den;
+  const i128 den = 2 * An * An - Cn * Cn;
+  // c1 = 2 / beta = 4 An Ad / den, c2 = -1 / (alpha beta) = -2 Ad^2 / den, then rescaled
+  const i128 q[2][2] = {{4 * An * Ad * scale_num, den * scale_den},
+                        {-2 * Ad * Ad * scale_num * scale_num, den * scale_den * scale_den}};
+  bfp_scalar* out[2] = {c1, c2};
+  auto bitlen = [](i128 v) { int b = 0; while (v > 0) { ++b; v >>= 1; } return b; };
+  for (int k = 0; k < 2; ++k) {
+    const bool neg = (q[k][0] < 0) != (q[k][1] < 0);
+    const i128 N = q[k][0] < 0 ? -q[k][0] : q[k][0];
+    const i128 D = q[k][1] < 0 ? -q[k][1] : q[k][1];
+    // fl = floor(log2(N / D)): the largest fl with D 2^fl <= N
+    auto le = [&](int f) { return f >= 0 ? (D << f) <= N : D <= (N << -f); };
+    int fl = bitlen(N) - bitlen(D) - 1;
+    while (!le(fl)) --fl;
+    while (le(fl + 1)) ++fl;
+    // nu = floor(log2 q) + 2 for q > 0; for q < 0 it is ceil(log2 |q|) + 1
+    const bool pow2 = fl >= 0 ? (D << fl) == N : D == (N << -fl);
+    const int nu = neg ? (pow2 ? fl + 1 : fl + 2) : fl + 2;
+    const int e = nu - w;
+    i128 num = N, dd = D;
+    if (e <= 0) num <<= -e; else dd <<= e;
+    i128 m = num / dd;                        // floor of |q| / 2^e
+    if (neg) m = (num % dd) ? -(m + 1) : -m;  // floor of a negative quotient
+    out[k]->m = (int64_t)m;
+    out[k]->exp = e;
+    out[k]->w = w;
+  }
+  return BFP_OK;
+}
+
+int mg_params_init(int ndim, int L, int w, int progressive, int nu1, int nu2, int N,
+                   int policy, int eta_percent, mg_params* out) {
+  if (!out) return fail(BFP_EINVAL, "out is NULL");
+  if (ndim != 2 && ndim != 3) return fail(BFP_ESHAPE, "ndim must be 2 or 3");
+  if (L < 1 || L > MG_MAX_LEVELS) return fail(BFP_ESHAPE, "L must be in 1..%d", MG_MAX_LEVELS);
+  if (w < 1 || w > 32) return fail(BFP_EWIDTH, "w must be in 1..32");
+  if (eta_percent < 1 || eta_percent > 99) return fail(BFP_EINVAL, "eta_percent must be in 1..99");
+  std::memset(out, 0, sizeof *out);
+  out->ndim = ndim;
+  out->L = L;
+  out->nu1 = nu1;
+  out->nu2 = nu2;
+  out->N = N;
+  out->policy = policy;
+  for (int j = 1; j <= L; ++j) {
+    if (!progressive) {
+      out->w_check[j] = out->w_work[j] = out->w_inner[j] = w;
+    } else {
+      const int work = 2 * j + 8 < 32 ? 2 * j + 8 : 32;
+      int inner = w - (L - j);
+      if (inner < 5) inner = 5;
+      if (inner > work) inner = work;
+      out->w_check[j] = 32;
+      out->w_work[j] = work;
+      out->w_inner[j] = inner;
+    }
+  }
+  // D^-1 A = A' / a_c with a_c = 1 (2D) or 3/4 (3D): c1' = c1 / a_c, c2' = c2 / a_c^2
+  int rc = bfp_cheby_coeffs(2, 1, eta_percent, 100, ndim == 2 ? 1 : 4, ndim == 2 ? 1 : 3, 16,
+                            &out->c1, &out->c2);
+  if (rc) return rc;
+  bfp_scalar c2u;
+  rc = bfp_cheby_coeffs(2, 1, eta_percent, 100, 1, 1, 16, &out->c1_gamma, &c2u);
+  if (rc) return rc;
+  return check_params(out);
+}
+
+size_t mg_hierarchy_bytes(const mg_params* prm) {
+  if (check_params(prm)) return 0;
+  mg_hierarchy tmp;
+  return layout(&tmp, prm, nullptr);
+}
+
+int mg_hierarchy_create(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
+                        mg_hierarchy** out) {
+  int rc = check_params(prm);
+  if (rc) return rc;
+  if (!out || !arena_dev) return fail(BFP_EINVAL, "NULL argument");
+  if ((uintptr_t)arena_dev % 256) return fail(BFP_EINVAL, "arena must be 256-byte aligned");
+  mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
+  if (!h) return fail(BFP_ENOMEM, "host allocation failed");
+  h->prm = *prm;
+  const size_t need = layout(h, prm, nullptr);
+  if (bytes < need) {
+    delete h;
+    return fail(BFP_ENOMEM, "arena holds %zu bytes, the hierarchy needs %zu", bytes, need);
+  }
+  layout(h, prm, static_cast<char*>(arena_dev));
+  make_stencils(prm->ndim, &h->A, &h->R, &h->P);
+  // (2 c1 + 1) / 4 exactly: c1 = m 2^e
+  const bfp_scalar c = prm->c1_gamma;
+  if (c.exp + 1 >= 0) {
+    h->vres.m = (c.m << (c.exp + 1)) + 1;
+    h->vres.exp = -2;
+  } else {
+    h->vres.m = c.m + ((int64_t)1 << (-(c.exp + 1)));
+    h->vres.exp = c.exp - 1;
+  }
+  h->vres.w = 24;
+  while (h->vres.m % 2 == 0) { h->vres.m /= 2; h->vres.exp += 1; }
+  if (h->vres.m >= (1 << 23)) {
+    delete h;
+    return fail(BFP_EWIDTH, "(2 c1 + 1) / 4 needs more than 24 bits");
+  }
+  for (int j = 1; j <= prm->L; ++j) {
+    Level& L = h->lv[j];
+    for (bfp_vec* v : {&L.x, &L.b, &L.r, &L.vr, &L.y, &L.s, &L.t}) {
+      if ((rc = bfp_vec_init(v, stream))) { delete h; return rc; }
+    }
+  }
+  *out = h;
+  return BFP_OK;
+}
+
+int mg_hierarchy_destroy(mg_hierarchy* h) {
+  delete h;
+  return BFP_OK;
+}
+
+int mg_set_rhs(mg_hierarchy* h, int level, const double* f_dev, void* stream) {
+  if (!h || level < 1 || level > h->prm.L) return fail(BFP_EINVAL, "bad level");
+  const int64_t shift = h->prm.ndim == 2 ? -2 * level - 2 : -2 * level - 3;
+  return bfp_vec_from_f64(f_dev, shift, &h->lv[level].b, stream);
+}
+
+int mg_set_x(mg_hierarchy* h, int level, const double* x0_dev, void* stream) {
+  if (!h || level < 1 || level > h->prm.L) return fail(BFP_EINVAL, "bad level");
+  return bfp_vec_from_f64(x0_dev, 0, &h->lv[level].x, stream);
+}
+
+int mg_vcycle(mg_hierarchy* h, int level, const bfp_vec* r, bfp_vec* y, void* stream) {
+  if (!h || level < 1 || level > h->prm.L || !r || !y) return fail(BFP_EINVAL, "bad argument");
+  int rc = vcycle(h, level, *r, (hipStream_t)stream);
+  if (rc) return rc;
+  *y = h->lv[level].y;
+  return BFP_OK;
+}
+
+int mg_ir(mg_hierarchy* h, int level, int iters, void* stream) {
+  if (!h || level < 1 || level > h->prm.L || iters < 0) return fail(BFP_EINVAL, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  Level& L = h->lv[level];
+  for (int i = 1; i <= iters; ++i) {
+    bfp_gamma g = g_norm(L.r, kOne);
+    const bool plain_first2 = h->prm.policy == MG_POLICY_NN_IR_FIRST2_Q && i <= 2;
+    int rc = ir_iteration(h, level, i == 1 ? nullptr : &g, i == 1, plain_first2, s);
+    if (rc) return rc;
+  }
+  return BFP_OK;
+}
+
+int mg_fmg(mg_hierarchy* h, void* stream) {
+  if (!h) return fail(BFP_EINVAL, "NULL hierarchy");
+  hipStream_t s = (hipStream_t)stream;
+  const mg_params& p = h->prm;
+  int rc;
+  if ((rc = bfp_vec_init(&h->lv[1].x, s))) return rc;
+  h->launches += 2;
+  for (int l = 1; l <= p.L; ++l) {
+    Level& L = h->lv[l];
+    if (l > 1) {
+      Level& C = h->lv[l - 1];
+      if ((rc = op_stencil(h, &h->P, C.x, &kOne, nullptr, nullptr, L.x,
+                           mode_for(h, kFmgProl, false), g_norm(C.x, kOne), s)))
+        return rc;
+    }
+    for (int i = 1; i <= p.N; ++i) {
+      bfp_gamma g = i > 1 ? g_norm(L.r, kOne)
+                          : (l > 1 ? g_norm(h->lv[l - 1].r, kOne) : g_norm(L.b, kOne));
+      if ((rc = ir_iteration(h, l, &g, i == 1, false, s))) return rc;
+    }
+  }
+  return BFP_OK;
+}
+
+int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out) {
+  if (!h || !out || level < 1 || level > h->prm.L) return fail(BFP_EINVAL, "bad argument");
+  Level& L = h->lv[level];
+  switch (which) {
+    case 0: *out = L.x; return BFP_OK;
+    case 1: *out = L.b; return BFP_OK;
+    case 2: *out = L.r; return BFP_OK;
+    case 3: *out = L.y; return BFP_OK;
+  }
+  return fail(BFP_EINVAL, "unknown block %d", which);
+}
+
+int mg_counters(const mg_hierarchy* h, double* bytes, int64_t* launches) {
+  if (!h) return fail(BFP_EINVAL, "NULL hierarchy");
+  if (bytes) *bytes = h->bytes;
+  if (launches) *launches = h->launches;
+  return BFP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,285 @@
+"""Bit-exact parity of every BFP operation of the HIP library against the
+oracle (mantissas, exponent and max/min metadata), through the C-ABI."""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2307_00124_amd as P
+import workloads as W
+from oracle import blas, fd
+from oracle.bfp import BFP, Scalar, as_block, from_f64
+from tests.gpu_util import assert_block_equal, download, rand_block, upload
+
+pytestmark = pytest.mark.gpu
+
+TWO = Fraction(2)
+
+
+def offsets(ndim):
+    return list(itertools.product((-1, 0, 1), repeat=ndim))
+
+
+def pair(kind: str, ndim: int, exp: int, taps: dict):
+    """The same BFP matrix for the library (tap array) and the oracle."""
+    kinds = {"A": P.BFP_STENCIL_A, "R": P.BFP_STENCIL_R, "P": P.BFP_STENCIL_P}
+    arr = [int(taps.get(o, 0)) for o in offsets(ndim)]
+    mA = {"A": 2 * ndim + 1, "R": 3 ** ndim, "P": 2 ** ndim}[kind]
+    nz = {o: t for o, t in taps.items() if t}
+    w = max(((t if t >= 0 else ~t).bit_length() + 1) for t in nz.values())
+    return P.Stencil(ndim, kinds[kind], exp, arr, w), fd.Stencil(kind, ndim, exp, nz, w, mA)
+
+
+def star(ndim, g, exp=-2):
+    t = {o: 0 for o in offsets(ndim)}
+    for o in offsets(ndim):
+        l1 = sum(abs(c) for c in o)
+        if l1 == 0:
+            t[o] = int(g.integers(-(1 << 10), 1 << 10))
+        elif l1 == 1:
+            t[o] = int(g.integers(-(1 << 10), 1 << 10))
+    return pair("A", ndim, exp, t)
+
+
+def fd_A(ndim):
+    s = fd.scaled_A(5, ndim)
+    return pair("A", ndim, s.e, s.taps)
+
+
+def gamma_pair(kind, g, x_or, x_dev, y_or=None, y_dev=None):
+    """(library estimate, oracle Fraction)"""
+    if kind == "norm":
+        c = P.scalar(int(g.integers(1, 1 << 15)), int(g.integers(-20, 5)))
+        return P.gamma_norm(x_dev, c), Fraction(c.m) * TWO ** c.exp * x_or.norm_inf()
+    if kind == "sum":
+        return P.gamma_sum(x_dev, y_dev), x_or.norm_inf() + y_or.norm_inf()
+    if kind == "zero":
+        return P.gamma_explicit(0, 0), Fraction(0)
+    m = int(g.integers(1, 1 << 20))
+    e = int(g.integers(-40, 40))
+    return P.gamma_explicit(m, e), Fraction(m) * TWO ** e
+
+
+def quantize_ref(op, mode, w_out, gamma):
+    if mode == P.BFP_NORMALIZE:
+        return blas.qcomp_plain(op, w_out)[0]
+    return blas.nnqcomp(op, w_out, gamma)[0]
+
+
+# ---------------------------------------------------------- conversion --
+
+@pytest.mark.parametrize("ndim,n", [(2, 1), (2, 9), (2, 300), (3, 1), (3, 13)])
+@pytest.mark.parametrize("w,bits", [(1, 8), (8, 8), (12, 16), (24, 32), (32, 32)])
+def test_from_f64(ndim, n, w, bits):
+    g = np.random.default_rng(n * 100 + w)
+    x = g.standard_normal((n + 2,) * ndim) * np.exp2(g.integers(-30, 30, (n + 2,) * ndim))
+    x[(0,) * ndim] = 5.0          # ring values are ignored
+    flat = x.reshape(-1)
+    flat[g.integers(0, flat.size, 3)] = 0.0
+    flat[g.integers(0, flat.size, 2)] = 5e-324      # subnormal
+    flat[g.integers(0, flat.size, 2)] = -2.0 ** -1060
+    inner = np.zeros_like(x, dtype=bool)
+    inner[(slice(1, -1),) * ndim] = True
+    xr = np.where(inner, x, 0.0)
+    for shift in (0, -13, 7):
+        v = P.Vec(ndim, n, w, bits)
+        P.bfp_vec_from_f64(torch.from_numpy(x).cuda(), shift, v)
+        ref = from_f64(xr, w)
+        ref = BFP(ref.e + shift, ref.m, w)
+        assert_block_equal(v, ref, f"from_f64 shift {shift}")
+        back = P.bfp_vec_to_f64(v).cpu().numpy()
+        assert np.array_equal(back, ref.to_f64())
+
+
+def test_from_f64_zero_and_nonfinite():
+    v = P.Vec(2, 5, 16)
+    P.bfp_vec_from_f64(torch.zeros(49, dtype=torch.float64, device="cuda"), 3, v)
+    e, m, meta = download(v)
+    assert e == 1 - 16 + 3 and not m.any()
+    x = torch.zeros(49, dtype=torch.float64)
+    x[10] = float("nan")
+    P.bfp_vec_from_f64(x.cuda(), 0, v)
+    with pytest.raises(P.BFPError) as ei:
+        P.bfp_vec_check(v)
+    assert ei.value.code == -4
+
+
+# ------------------------------------------------------------ stencils --
+
+STORAGE = [(32, 32, 32), (16, 32, 8), (8, 16, 16), (32, 8, 16)]
+
+
+@pytest.mark.parametrize("ndim,n", [(2, 1), (2, 7), (2, 37), (2, 300), (3, 1), (3, 5), (3, 19)])
+@pytest.mark.parametrize("mode", [P.BFP_SATURATE, P.BFP_NORMALIZE])
+@pytest.mark.parametrize("with_y", [False, True])
+def test_star_stencil(ndim, n, mode, with_y):
+    g = np.random.default_rng(ndim * 1000 + n * 10 + mode * 3 + with_y)
+    for case, (bx, by, bz) in enumerate(STORAGE):
+        wx = int(g.integers(1, bx + 1))
+        wy = int(g.integers(1, by + 1))
+        wz = int(g.integers(1, bz + 1))
+        Ad, Ao = fd_A(ndim) if case % 2 == 0 else star(ndim, g, int(g.integers(-8, 8)))
+        x = rand_block(g, ndim, n, wx, int(g.integers(-40, 40)))
+        y = rand_block(g, ndim, n, wy, int(g.integers(-40, 40))) if with_y else None
+        al = Scalar(int(g.integers(-(1 << 15), 1 << 15)) or 1, int(g.integers(-10, 10)), 16)
+        be = Scalar(int(g.integers(-(1 << 15), 1 << 15)) or -1, int(g.integers(-10, 10)), 16)
+        if case == 3:
+            al, be = Scalar(1, 0, 2), Scalar(-1, 0, 1)
+        xd = upload(x, bx)
+        yd = upload(y, by) if with_y else None
+        gk = ["explicit", "norm", "sum" if with_y else "norm", "zero"][case]
+        gd, gr = gamma_pair(gk, g, x, xd, y, yd)
+        z = P.Vec(ndim, n, wz, bz)
+        P.bfp_stencil_apply(Ad, xd, P.scalar(al.m, al.e), P.scalar(be.m, be.e), yd, wz, mode,
+                            gd, z)
+        op = blas.gemv(Ao, x, y, al, be) if with_y else blas.spmv(Ao, x)
+        if not with_y:
+            op = blas.Exact(op.e + al.e, op.w + 16, (lambda o=op, a=al: a.m * o.rows()))
+        ref = quantize_ref(op, mode, wz, gr)
+        assert_block_equal(z, ref, f"case {case} storage {(bx, by, bz)} gamma {gk}")
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_huge_exponent_gaps(ndim):
+    """alpha A x + beta y with operand exponents more than 64 apart (the
+    128-bit and beyond-128-bit branches of the exact msb)."""
+    g = np.random.default_rng(7 + ndim)
+    n = 9 if ndim == 2 else 5
+    Ad, Ao = fd_A(ndim)
+    for gap in (63, 64, 65, 90, 200, -70, -130):
+        x = rand_block(g, ndim, n, 32, 0)
+        y = rand_block(g, ndim, n, 20, -gap)
+        xd, yd = upload(x), upload(y)
+        for mode in (P.BFP_NORMALIZE, P.BFP_SATURATE):
+            z = P.Vec(ndim, n, 24, 32)
+            gd, gr = gamma_pair("sum", g, x, xd, y, yd)
+            P.bfp_stencil_apply(Ad, xd, P.scalar(3, 0), P.scalar(-5, 0), yd, 24, mode, gd, z)
+            op = blas.gemv(Ao, x, y, Scalar(3, 0, 3), Scalar(-5, 0, 4))
+            assert_block_equal(z, quantize_ref(op, mode, 24, gr), f"gap {gap} mode {mode}")
+
+
+# ------------------------------------------------------------ transfers --
+
+@pytest.mark.parametrize("ndim,nc", [(2, 1), (2, 3), (2, 15), (2, 150), (3, 1), (3, 3), (3, 9)])
+@pytest.mark.parametrize("kind", ["R", "P"])
+@pytest.mark.parametrize("mode", [P.BFP_SATURATE, P.BFP_NORMALIZE])
+def test_transfers(ndim, nc, kind, mode):
+    g = np.random.default_rng(ndim * 31 + nc * 7 + (kind == "P") * 3 + mode)
+    nf = 2 * nc + 1
+    for case, (bx, by, bz) in enumerate(STORAGE):
+        if case % 2 == 0:
+            S = fd.scaled_R(5, ndim) if kind == "R" else fd.prolongation(ndim)
+            Sd, So = pair(kind, ndim, S.e, S.taps)
+        else:
+            taps = {o: int(g.integers(-(1 << 8), 1 << 8)) for o in offsets(ndim)}
+            Sd, So = pair(kind, ndim, int(g.integers(-6, 3)), taps)
+        n_in, n_out = (nf, nc) if kind == "R" else (nc, nf)
+        x = rand_block(g, ndim, n_in, int(g.integers(1, bx + 1)), int(g.integers(-20, 20)))
+        with_y = case >= 2
+        wz = int(g.integers(1, bz + 1))
+        y = rand_block(g, ndim, n_out, int(g.integers(1, by + 1)), int(g.integers(-20, 20))) \
+            if with_y else None
+        xd = upload(x, bx)
+        yd = upload(y, by) if with_y else None
+        gd, gr = gamma_pair("norm" if case % 2 else "explicit", g, x, xd)
+        z = P.Vec(ndim, n_out, wz, bz)
+        al, be = (Scalar(-1, 0, 1), Scalar(1, 0, 2)) if with_y else (Scalar(1, 0, 2), None)
+        P.bfp_stencil_apply(Sd, xd, P.scalar(al.m, al.e), P.scalar(be.m, be.e) if be else None,
+                            yd, wz, mode, gd, z)
+        op = blas.gemv(So, x, y, al, be) if with_y else blas.spmv(So, x)
+        assert_block_equal(z, quantize_ref(op, mode, wz, gr), f"{kind} case {case}")
+
+
+# ------------------------------------------------------------ pointwise --
+
+@pytest.mark.parametrize("ndim,n", [(2, 1), (2, 64), (2, 257), (3, 7)])
+@pytest.mark.parametrize("mode", [P.BFP_SATURATE, P.BFP_NORMALIZE])
+def test_axpy_and_sub(ndim, n, mode):
+    g = np.random.default_rng(n * 3 + mode + ndim)
+    for case, (bx, by, bz) in enumerate(STORAGE):
+        x = rand_block(g, ndim, n, int(g.integers(1, bx + 1)), int(g.integers(-50, 50)))
+        y = rand_block(g, ndim, n, int(g.integers(1, by + 1)), int(g.integers(-50, 50)))
+        xd, yd = upload(x, bx), upload(y, by)
+        wz = int(g.integers(1, bz + 1))
+        gd, gr = gamma_pair("sum" if case % 2 else "explicit", g, x, xd, y, yd)
+        al = Scalar(int(g.integers(-(1 << 20), 1 << 20)) or 3, int(g.integers(-30, 30)), 21)
+        be = Scalar(int(g.integers(-(1 << 20), 1 << 20)) or 5, int(g.integers(-30, 30)), 21)
+        z = P.Vec(ndim, n, wz, bz)
+        P.bfp_axpy(P.scalar(al.m, al.e), xd, P.scalar(be.m, be.e), yd, wz, mode, gd, z)
+        assert_block_equal(z, quantize_ref(blas.axpby(al, x, be, y), mode, wz, gr), "axpy")
+        z2 = P.Vec(ndim, n, wz, bz)
+        P.bfp_sub(xd, yd, wz, mode, gd, z2)
+        assert_block_equal(z2, quantize_ref(blas.sub(x, y), mode, wz, gr), "sub")
+        # in place: z aliases y
+        P.bfp_sub(xd, yd, min(wz, by), mode, gd, yd)
+        assert_block_equal(yd, quantize_ref(blas.sub(x, y), mode, min(wz, by), gr), "sub in place")
+
+
+@pytest.mark.parametrize("ndim,n", [(2, 5), (2, 200), (3, 6)])
+def test_normalize_and_saturate_truncate(ndim, n):
+    g = np.random.default_rng(n + ndim)
+    for bits in (8, 16, 32):
+        for w_in in (1, bits // 2, bits):
+            x = rand_block(g, ndim, n, w_in, int(g.integers(-9, 9)))
+            xd = upload(x, bits)
+            for w_out in (1, 3, bits):
+                z = P.Vec(ndim, n, w_out, bits)
+                P.bfp_normalize(xd, w_out, z)
+                assert_block_equal(z, blas.normalize(x, w_out), "normalize")
+                gd, gr = gamma_pair("explicit", g, x, xd)
+                P.bfp_saturate_truncate(xd, w_out, gd, z)
+                assert_block_equal(z, blas.saturate_truncate(x, w_out, gr)[0], "sat_trunc")
+    # zero block normalizes to e + 1 - w
+    zb = rand_block(g, ndim, n, 8, 3)
+    zb.m[...] = 0
+    zd = upload(zb, 8)
+    out = P.Vec(ndim, n, 5, 8)
+    P.bfp_normalize(zd, 5, out)
+    assert_block_equal(out, blas.normalize(zb, 5), "normalize zero")
+
+
+def test_saturation_count_metadata():
+    g = np.random.default_rng(3)
+    x = rand_block(g, 2, 40, 20, 0)
+    xd = upload(x, 32)
+    z = P.Vec(2, 40, 6, 8)
+    P.bfp_saturate_truncate(xd, 6, P.gamma_explicit(1, 10), z)
+    ref, info = blas.saturate_truncate(x, 6, Fraction(1 << 10))
+    assert_block_equal(z, ref, "saturate")
+    assert z.host_meta()[P.BFP_META_SAT] == info.saturated > 0
+
+
+@pytest.mark.parametrize("ndim,n", [(2, 1), (2, 50), (2, 1000), (3, 40)])
+def test_dot(ndim, n):
+    g = np.random.default_rng(n)
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    for bx, by in ((32, 32), (16, 8), (32, 16)):
+        x = rand_block(g, ndim, n, bx, int(g.integers(-20, 20)))
+        y = rand_block(g, ndim, n, by, int(g.integers(-20, 20)))
+        xd, yd = upload(x, bx), upload(y, by)
+        P.bfp_dot(xd, yd, out)
+        o = [int(v) for v in out.cpu().tolist()]
+        m = (o[1] << 64) + (o[0] & ((1 << 64) - 1))
+        ref = blas.dot(x, y)
+        assert (m, o[2]) == (ref.m, ref.e)
+        assert o[3:7] == [0, 0, 0, 0]
+
+
+def test_repeated_calls_are_identical():
+    """The self-resetting reduction scratch leaves nothing behind."""
+    g = np.random.default_rng(11)
+    Ad, Ao = fd_A(2)
+    x = rand_block(g, 2, 129, 32, -5)
+    xd = upload(x)
+    outs = []
+    for _ in range(4):
+        z = P.Vec(2, 129, 17, 32)
+        P.bfp_stencil_apply(Ad, xd, None, None, None, 17, P.BFP_NORMALIZE, None, z)
+        outs.append(download(z))
+    for e, m, meta in outs[1:]:
+        assert e == outs[0][0] and (m == outs[0][1]).all() and meta[:8] == outs[0][2][:8]
+    assert outs[0][2][8:13] == [-(1 << 63), (1 << 63) - 1, 0, 0, 0]

@@ -59,7 +59,7 @@ typedef enum {
  *     X_w_out). One pass. A zero gamma gives e_out = e_z* + 1 - w_out. */
 typedef enum { BFP_NORMALIZE = 0, BFP_SATURATE = 1 } bfp_mode;
 
-/* Device metadata of a block: BFP_META_SLOTS int64 values.
+/* Device metadata of a block: BFP_META_SLOTS int64 values (2304 bytes).
  *   [BFP_META_EXP] shared exponent e
  *   [BFP_META_MAX] largest mantissa, [BFP_META_MIN] smallest mantissa
  *                  (both taken over the whole padded array, ring included,
@@ -67,9 +67,11 @@ typedef enum { BFP_NORMALIZE = 0, BFP_SATURATE = 1 } bfp_mode;
  *   [BFP_META_SAT] entries saturated by the operation that wrote the block
  *   [BFP_META_MU]  mu* of the last BFP_NORMALIZE operation writing the block
  *   [BFP_META_FLAGS] bit 0: non-finite FP64 input seen by bfp_vec_from_f64
- *   slots 8..15 are the library's reduction scratch; bfp_vec_init (or a
- *   zero fill followed by bfp_meta_reset) must prepare them once. */
-#define BFP_META_SLOTS 16
+ *   slots 16..287 are the library's reduction scratch (a ticket counter and
+ *   sixteen accumulator sets on separate cache lines); bfp_vec_init (or
+ *   bfp_meta_reset) must prepare them once, and every operation leaves them
+ *   prepared again. */
+#define BFP_META_SLOTS 288
 #define BFP_META_EXP 0
 #define BFP_META_MAX 1
 #define BFP_META_MIN 2
@@ -200,10 +202,10 @@ int bfp_sub(const bfp_vec* x, const bfp_vec* y, int w_out, int mode, const bfp_g
 
 /* Exact dot product sum_i x_m,i * y_m,i (Section 2 remark on BFP dot
  * products: no alignment shifts, exponent e_x + e_y, accumulator growing
- * with log2 n). out_dev: 8 int64, of which [0] = low and [1] = high 64 bits
- * of the two's-complement 128-bit mantissa, [2] = exponent; [3..7] are the
- * library's reduction scratch and must be zero before the first call (they
- * are left zero after every call).                                        */
+ * with log2 n). out_dev: BFP_META_SLOTS int64, of which [0] = low and
+ * [1] = high 64 bits of the two's-complement 128-bit mantissa, [2] =
+ * exponent; [16..] are the library's reduction scratch and must be zero
+ * before the first call (they are left zero after every call).            */
 int bfp_dot(const bfp_vec* x, const bfp_vec* y, int64_t* out_dev, void* stream);
 
 /* ------------------------------------------------ a7, a8: requantization */
@@ -308,6 +310,12 @@ int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out);
 /* Per-level algorithmic byte counts of everything enqueued so far, and
  * the number of kernel launches (host-side counters).                     */
 int mg_counters(const mg_hierarchy* h, double* bytes, int64_t* launches);
+
+/* Launch-shape tuning of the star stencil kernels (process-wide; results
+ * do not depend on it): "star2d_rows" / "star3d_rows" = rows or planes one
+ * wave marches on large grids, "star2d_small_n" / "star3d_small_n" = grid
+ * size below which every wave takes a single row.                        */
+int bfp_tuning_set(const char* key, int value);
 
 /* Human-readable description of the last error on this thread.           */
 const char* bfp_last_error(void);

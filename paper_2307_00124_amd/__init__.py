@@ -256,8 +256,8 @@ def bfp_sub(x: Vec, y: Vec, w_out: int, mode: int, gamma, z: Vec, stream=None) -
 
 
 def bfp_dot(x: Vec, y: Vec, out: torch.Tensor, stream=None) -> None:
-    if out.dtype != torch.int64 or out.numel() < 8:
-        raise ValueError("out must be an int64 device tensor of 8 zero-initialised slots")
+    if out.dtype != torch.int64 or out.numel() < BFP_META_SLOTS:
+        raise ValueError(f"out must be an int64 device tensor of {BFP_META_SLOTS} zeroed slots")
     check(lib.bfp_dot(C.byref(x.c), C.byref(y.c), _ptr(out), _stream(stream)), "bfp_dot")
 
 
@@ -269,6 +269,10 @@ def bfp_normalize(x: Vec, w_out: int, out: Vec, stream=None) -> None:
 def bfp_saturate_truncate(x: Vec, w_out: int, gamma, out: Vec, stream=None) -> None:
     check(lib.bfp_saturate_truncate(C.byref(x.c), w_out, _opt(gamma), C.byref(out.c),
                                     _stream(stream)), "bfp_saturate_truncate")
+
+
+def bfp_tuning_set(key: str, value: int) -> None:
+    check(lib.bfp_tuning_set(key.encode(), int(value)), "bfp_tuning_set")
 
 
 def bfp_cheby_coeffs(rho: tuple[int, int], eta: tuple[int, int], scale: tuple[int, int] = (1, 1),

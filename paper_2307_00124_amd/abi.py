@@ -18,7 +18,7 @@ BFP_ENOMEM, BFP_EHIP, BFP_EBUSY, BFP_ENOTFOUND, BFP_PENDING = -5, -6, -7, -8, 1
 BFP_NORMALIZE, BFP_SATURATE = 0, 1
 BFP_STENCIL_A, BFP_STENCIL_R, BFP_STENCIL_P = 0, 1, 2
 BFP_GAMMA_NORM, BFP_GAMMA_SUM, BFP_GAMMA_EXPLICIT = 1, 2, 3
-BFP_META_SLOTS = 16
+BFP_META_SLOTS = 288
 BFP_META_EXP, BFP_META_MAX, BFP_META_MIN, BFP_META_SAT, BFP_META_MU, BFP_META_FLAGS = range(6)
 MG_POLICY_Q, MG_POLICY_NN, MG_POLICY_NN_IR_FIRST_Q, MG_POLICY_NN_IR_FIRST2_Q, MG_POLICY_NN_IR_Q = range(5)
 MG_MAX_LEVELS = 16
@@ -90,6 +90,7 @@ SIGNATURES = {
     "mg_vcycle": (I, [VP, I, P(bfp_vec), P(bfp_vec), VP]),
     "mg_get_vec": (I, [VP, I, I, P(bfp_vec)]),
     "mg_counters": (I, [VP, P(C.c_double), P(I64)]),
+    "bfp_tuning_set": (I, [C.c_char_p, I]),
     "bfp_last_error": (C.c_char_p, []),
 }
 

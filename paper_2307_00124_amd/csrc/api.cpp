@@ -17,6 +17,18 @@ namespace bfpk {
 
 static thread_local std::string g_last_error;
 
+// Launch-shape tuning (rows or planes marched by one wave in the star
+// kernels, chosen per grid size): rows = 1 below the threshold n, then
+// `rows_large` (latency-bound small grids want many independent waves,
+// large grids want longer marches that reuse the line window).
+static int g_star2d_rows_large = 16, g_star2d_small_n = 512;
+static int g_star3d_rows_large = 16, g_star3d_small_n = 64;
+
+static int star_rows(int ndim, int64_t n) {
+  if (ndim == 2) return n < g_star2d_small_n ? 1 : g_star2d_rows_large;
+  return n < g_star3d_small_n ? 1 : g_star3d_rows_large;
+}
+
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -216,7 +228,7 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
     L.ybits = y ? y->storage_bits : 32;
     L.zbits = z->storage_bits;
     L.wide = wide;
-    L.rows = rows > 0 ? rows : (x->ndim == 2 ? 8 : 16);
+    L.rows = rows > 0 ? rows : star_rows(x->ndim, x->n);
     return run_modes(L, mode, [&](StarLaunch& l) { return launch_star(l, s); });
   }
   if (A->kind == BFP_STENCIL_R || A->kind == BFP_STENCIL_P) {
@@ -401,6 +413,18 @@ int bfp_saturate_truncate(const bfp_vec* in, int w_out, const bfp_gamma* gamma, 
   bfp_scalar one{1, 0, 2};
   return point_impl(&one, in, nullptr, nullptr, w_out, BFP_SATURATE, gamma, out,
                     (hipStream_t)stream, -1);
+}
+
+int bfp_tuning_set(const char* key, int value) {
+  if (!key) return fail(BFP_EINVAL, "key is NULL");
+  if (value < 1 || value > 1 << 20) return fail(BFP_EINVAL, "value out of range");
+  const std::string k(key);
+  if (k == "star2d_rows") g_star2d_rows_large = value;
+  else if (k == "star2d_small_n") g_star2d_small_n = value;
+  else if (k == "star3d_rows") g_star3d_rows_large = value;
+  else if (k == "star3d_small_n") g_star3d_small_n = value;
+  else return fail(BFP_EINVAL, "unknown tuning key %s", key);
+  return BFP_OK;
 }
 
 int bfp_vec_assign(bfp_vec* v, int64_t exp, void* stream) {

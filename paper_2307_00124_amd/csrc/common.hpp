@@ -6,14 +6,20 @@
 
 namespace bfpk {
 
-constexpr int kBlock = 256;  // threads per workgroup for every kernel
+constexpr int kBlock = 256;       // threads per workgroup for every kernel
+constexpr int kMaxBlocks = 2048;  // grid-stride kernels launch at most this many
 
-// metadata slots (see include/bfpmg.h); 8.. are reduction scratch
+// metadata slots (see include/bfpmg.h); 16.. are reduction scratch: a
+// top-level ticket and kSets accumulator sets (max, min, saturations, mu*,
+// set ticket), each set in its own 128-byte line; a block uses set
+// (linear block index mod kSets), which spreads a launch's atomics over
+// kSets addresses.
 constexpr int kMetaExp = 0, kMetaMax = 1, kMetaMin = 2, kMetaSat = 3, kMetaMu = 4,
               kMetaFlags = 5;
-constexpr int kMetaAccMax = 8, kMetaAccMin = 9, kMetaAccSat = 10, kMetaAccMu = 11,
-              kMetaTicket = 12;
-constexpr int kMetaSlots = 16;
+constexpr int kMetaTicket = 16;
+constexpr int kSets = 16, kSetBase = 32, kSetStride = 16;
+constexpr int kAccMax = 0, kAccMin = 1, kAccSat = 2, kAccMu = 3, kAccTicket = 4;  // in a set
+constexpr int kMetaSlots = kSetBase + kSets * kSetStride;           // 288
 
 constexpr int kGammaNorm = 1, kGammaSum = 2, kGammaExplicit = 3;
 

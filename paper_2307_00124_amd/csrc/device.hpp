@@ -149,23 +149,76 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
   return v;
 }
 
-__device__ __forceinline__ int64_t atomic_load64(const int64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void atomic_store64(int64_t* p, int64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// ---------------------------------------------------- grid reductions --
+//
+// A launch reduces per-block partials into accumulator sets in the output
+// metadata and the last block to finish publishes the result and resets the
+// sets. All cross-block traffic goes through device-scope atomic
+// read-modify-writes (coherent across XCDs); a block's accumulator atomics
+// return before it takes its ticket (s_waitcnt vmcnt(0)), so the block that
+// draws the last ticket sees every contribution. No cache write-back or
+// invalidation fence is needed, and the scratch is left ready for the next
+// launch without a reset kernel.
+
+__device__ __forceinline__ unsigned block_linear() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 
-// Reduce the per-thread (max, min, saturations) of a block's outputs, merge
-// them into the output metadata's scratch slots, and let the last block of
-// the grid publish exponent / max / min / saturation count and reset the
-// scratch. Works for any grid size; the scratch is left ready for the next
-// launch, so no separate reset kernel is needed. Block size: kBlock.
+__device__ __forceinline__ int64_t* acc_set(int64_t* meta) {
+  return meta + kSetBase + kSetStride * (int)(block_linear() % kSets);
+}
+
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ int64_t amax(int64_t* p, int64_t v) {
+  return (int64_t)atomicMax((long long*)p, (long long)v);
+}
+__device__ __forceinline__ int64_t amin(int64_t* p, int64_t v) {
+  return (int64_t)atomicMin((long long*)p, (long long)v);
+}
+__device__ __forceinline__ int64_t aadd(int64_t* p, int64_t v) {
+  return (int64_t)atomicAdd((unsigned long long*)p, (unsigned long long)v);
+}
+__device__ __forceinline__ int64_t axch(int64_t* p, int64_t v) {
+  return (int64_t)atomicExch((unsigned long long*)p, (unsigned long long)v);
+}
+
+// Returns true (in the calling thread) when this block finished last. The
+// argument keeps the caller's accumulator atomics returning (their results
+// are consumed), so the wait below covers them. Tickets are two-level: a
+// block counts itself in its set; the last block of a set counts the set at
+// the top level. One address never sees more than ~nblocks / kSets atomics.
+__device__ __forceinline__ bool take_ticket(int64_t* meta, int64_t returned) {
+  __shared__ volatile int64_t s_sink;
+  s_sink = returned;
+  wait_vmem();
+  const unsigned nblk = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned b = block_linear();
+  const unsigned k = b % kSets;
+  const unsigned in_set = (nblk - k + kSets - 1) / kSets;          // blocks of set k
+  const unsigned used = nblk < (unsigned)kSets ? nblk : (unsigned)kSets;
+  int64_t* set = meta + kSetBase + kSetStride * (int)k;
+  if ((unsigned)aadd(&set[kAccTicket], 1) != in_set - 1) return false;
+  axch(&set[kAccTicket], 0);
+  return (unsigned)aadd(&meta[kMetaTicket], 1) == used - 1;
+}
+
+__device__ __forceinline__ int64_t block_max(int64_t v, int64_t* red) {
+  const int tid = threadIdx.x;
+  v = wave_max(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  int64_t b = red[0];
+  for (int i = 1; i < kBlock / 64; ++i) b = red[i] > b ? red[i] : b;
+  return b;
+}
+
+// Reduce the per-thread (max, min, saturations) of a block's outputs; the
+// last block publishes exponent / max / min / saturation count.
 __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64_t tsat,
                                                int64_t* zm, int64_t e_out) {
   __shared__ int64_t s_red[3][kBlock / 64];
-  __shared__ int s_last;
-  const int tid = threadIdx.x + threadIdx.y * blockDim.x + threadIdx.z * blockDim.x * blockDim.y;
+  const int tid = threadIdx.x;
   tmax = wave_max(tmax);
   tmin = wave_min(tmin);
   tsat = wave_sum(tsat);
@@ -182,51 +235,54 @@ __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64
       bmin = s_red[1][i] < bmin ? s_red[1][i] : bmin;
       bsat += s_red[2][i];
     }
-    atomicMax((long long*)&zm[kMetaAccMax], (long long)bmax);
-    atomicMin((long long*)&zm[kMetaAccMin], (long long)bmin);
-    if (bsat) atomicAdd((unsigned long long*)&zm[kMetaAccSat], (unsigned long long)bsat);
-    __threadfence();
-    const unsigned long long nblk = (unsigned long long)gridDim.x * gridDim.y * gridDim.z;
-    unsigned long long t = atomicAdd((unsigned long long*)&zm[kMetaTicket], 1ull);
-    s_last = (t == nblk - 1);
-    if (s_last) {
-      __threadfence();
-      int64_t mx = atomic_load64(&zm[kMetaAccMax]);
-      int64_t mn = atomic_load64(&zm[kMetaAccMin]);
-      int64_t st = atomic_load64(&zm[kMetaAccSat]);
+    if (gridDim.x * gridDim.y * gridDim.z == 1) {   // the block holds the whole result
+      zm[kMetaMax] = bmax;
+      zm[kMetaMin] = bmin;
+      zm[kMetaSat] = bsat;
+      zm[kMetaExp] = e_out;
+      return;
+    }
+    int64_t* set = acc_set(zm);
+    int64_t r = amax(&set[kAccMax], bmax) ^ amin(&set[kAccMin], bmin);
+    if (bsat) r ^= aadd(&set[kAccSat], bsat);
+    if (take_ticket(zm, r)) {
+      int64_t mx = INT64_MIN, mn = INT64_MAX, st = 0;
+      for (int k = 0; k < kSets; ++k) {
+        int64_t* sk = zm + kSetBase + kSetStride * k;
+        const int64_t a = axch(&sk[kAccMax], INT64_MIN);
+        const int64_t b = axch(&sk[kAccMin], INT64_MAX);
+        mx = a > mx ? a : mx;
+        mn = b < mn ? b : mn;
+        st += axch(&sk[kAccSat], 0);
+      }
+      axch(&zm[kMetaTicket], 0);
       zm[kMetaMax] = mx;
       zm[kMetaMin] = mn;
       zm[kMetaSat] = st;
       zm[kMetaExp] = e_out;
-      atomic_store64(&zm[kMetaAccMax], INT64_MIN);
-      atomic_store64(&zm[kMetaAccMin], INT64_MAX);
-      atomic_store64(&zm[kMetaAccSat], 0);
-      atomic_store64(&zm[kMetaTicket], 0);
     }
   }
 }
 
-// First pass of qcomp: reduce mu* = max(1, max msb(z*_i)) into the output
-// metadata; the last block stores it in kMetaMu.
+// First pass of qcomp: reduce mu* = max(1, max msb(z*_i)); the last block
+// stores it in kMetaMu.
 __device__ __forceinline__ void finish_mu(int64_t tmu, int64_t* zm) {
   __shared__ int64_t s_red[kBlock / 64];
-  const int tid = threadIdx.x + threadIdx.y * blockDim.x + threadIdx.z * blockDim.x * blockDim.y;
-  tmu = wave_max(tmu);
-  if ((tid & 63) == 0) s_red[tid >> 6] = tmu;
-  __syncthreads();
-  if (tid == 0) {
-    int64_t b = s_red[0];
-    for (int i = 1; i < kBlock / 64; ++i) b = s_red[i] > b ? s_red[i] : b;
-    atomicMax((long long*)&zm[kMetaAccMu], (long long)b);
-    __threadfence();
-    const unsigned long long nblk = (unsigned long long)gridDim.x * gridDim.y * gridDim.z;
-    unsigned long long t = atomicAdd((unsigned long long*)&zm[kMetaTicket], 1ull);
-    if (t == nblk - 1) {
-      __threadfence();
-      int64_t mu = atomic_load64(&zm[kMetaAccMu]);
-      zm[kMetaMu] = mu < 1 ? 1 : mu;
-      atomic_store64(&zm[kMetaAccMu], 0);
-      atomic_store64(&zm[kMetaTicket], 0);
+  const int64_t b = block_max(tmu, s_red);
+  if (threadIdx.x == 0 && gridDim.x * gridDim.y * gridDim.z == 1) {
+    zm[kMetaMu] = b < 1 ? 1 : b;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    int64_t* set = acc_set(zm);
+    if (take_ticket(zm, amax(&set[kAccMu], b))) {
+      int64_t mu = 1;
+      for (int k = 0; k < kSets; ++k) {
+        const int64_t a = axch(&zm[kSetBase + kSetStride * k + kAccMu], 0);
+        mu = a > mu ? a : mu;
+      }
+      axch(&zm[kMetaTicket], 0);
+      zm[kMetaMu] = mu;
     }
   }
 }

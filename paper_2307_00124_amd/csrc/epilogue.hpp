@@ -43,7 +43,14 @@ struct Epi {
   int64_t alpha_m, beta_m, lo, hi;
   int64_t D;       // first pass: exponent gap of the two terms
   int swap;        // first pass: the y term carries the larger exponent
-  int64_t tmax, tmin, tsat, tmu;
+  // fast path: the output exponent lies at or above both terms, so
+  // floor(hi 2^-Ls + lo 2^-Ll) = (hi + floor(lo / 2^(Ll-Ls))) >> Ls exactly,
+  // with no possible overflow (|hi|, |lo| < 2^61)
+  int fast;
+  int fswap, fd, fs;
+  int64_t tsat;
+  int32_t tmax, tmin;
+  int64_t tmu;
   int64_t* zm;
 
   __device__ __forceinline__ void init(const OpArgs& op) {
@@ -55,31 +62,68 @@ struct Epi {
     zm = op.z_meta;
     swap = R.ea < R.eb;
     D = swap ? R.eb - R.ea : R.ea - R.eb;
+    const int64_t sa = R.sa, sb = R.eb - R.eo;
+    if (HASY) {
+      fast = sa <= 0 && sb <= 0;
+      fswap = sa < sb;                       // the term with the larger shift is "hi"
+      const int64_t s_hi = fswap ? sb : sa, s_lo = fswap ? sa : sb;
+      const int64_t dd = s_hi - s_lo, ss = -s_hi;
+      fd = (int)(dd > 63 ? 63 : dd);
+      fs = (int)(ss > 63 ? 63 : ss);
+    } else {
+      fast = sa <= 0;
+      fswap = 0;
+      fd = 0;
+      fs = (int)(-sa > 63 ? 63 : -sa);
+    }
     tmax = 0;
     tmin = 0;
     tsat = 0;
     tmu = 1;
   }
 
-  // Process one interior output point; returns its mantissa (0 in pass 1).
-  __device__ __forceinline__ int64_t apply(int64_t g, int64_t yv) {
-    const int64_t a = alpha_m * g;
+  __device__ __forceinline__ int64_t mul_a(int64_t g) const {
+    return alpha_m == 1 ? g : (alpha_m == -1 ? -g : alpha_m * g);
+  }
+  __device__ __forceinline__ int64_t mul_b(int64_t y) const {
+    return beta_m == 1 ? y : (beta_m == -1 ? -y : beta_m * y);
+  }
+
+  // floor of the exact result at the output exponent (+-2^62 when beyond)
+  __device__ __forceinline__ int64_t value(int64_t g, int64_t yv) const {
+    const int64_t a = mul_a(g);
+    if (!HASY) return fast ? (a >> fs) : scale1(a, R.sa);
+    const int64_t b = mul_b(yv);
+    if (fast) {
+      const int64_t h = fswap ? b : a, l = fswap ? a : b;
+      return (h + (l >> fd)) >> fs;
+    }
+    return combine(R.cmb, a, b);
+  }
+
+  // Process one output point (inside = interior point of the output grid);
+  // returns its mantissa, 0 outside or in the first qcomp pass.
+  __device__ __forceinline__ int64_t put(int64_t g, int64_t yv, bool inside) {
     if (PASS == kQ1) {
+      const int64_t a = mul_a(g);
       int m;
       if (HASY) {
-        const int64_t b = beta_m * yv;
+        const int64_t b = mul_b(yv);
         m = swap ? msb_exact2(b, a, D) : msb_exact2(a, b, D);
       } else {
         m = msb64(a);
       }
+      m = inside ? m : 1;
       tmu = m > tmu ? m : tmu;
       return 0;
     }
-    int64_t v = HASY ? combine(R.cmb, a, beta_m * yv) : scale1(a, R.sa);
-    v = clamp64(v, lo, hi, tsat);
-    tmax = v > tmax ? v : tmax;
-    tmin = v < tmin ? v : tmin;
-    return v;
+    const int64_t v = value(g, yv);
+    const int64_t c = v < lo ? lo : (v > hi ? hi : v);
+    tsat += (inside && c != v) ? 1 : 0;
+    const int32_t r = inside ? (int32_t)c : 0;
+    tmax = r > tmax ? r : tmax;
+    tmin = r < tmin ? r : tmin;
+    return r;
   }
 
   __device__ __forceinline__ void finish() {

@@ -13,24 +13,34 @@ __device__ __forceinline__ int64_t interior_row(int64_t row, int64_t n, int nd) 
   return nd == 3 ? (row / n + 1) * (n + 2) + (row % n + 1) : row + 1;
 }
 
+// work items: (interior row, 1024-column chunk) pairs, grid-strided
+__host__ __device__ inline int64_t row_items(int64_t n, int ndim) {
+  return (ndim == 3 ? n * n : n) * ((n + 2 + 1023) / 1024);
+}
+inline unsigned grid_for(int64_t items) {
+  return (unsigned)(items < kMaxBlocks ? items : kMaxBlocks);
+}
+
 template <typename TX, typename TY, typename TZ, int PASS, bool HASY>
 __global__ __launch_bounds__(kBlock) void k_point(const PointLaunch L) {
   const int64_t n = L.n;
   const int64_t nchunk = (n + 2 + 1023) / 1024;
-  const int64_t rr = interior_row(blockIdx.x / nchunk, n, L.ndim);
-  const int64_t c = (int64_t)(blockIdx.x % nchunk) * 1024 + threadIdx.x * 4;
+  const int64_t items = row_items(n, L.ndim);
   const TX* X = static_cast<const TX*>(L.x);
   const TY* Y = static_cast<const TY*>(L.y);
   TZ* Z = static_cast<TZ*>(L.z);
   Epi<PASS, HASY> E;
   E.init(L.op);
-  if (c < n + 2) {
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t rr = interior_row(it / nchunk, n, L.ndim);
+    const int64_t c = (it % nchunk) * 1024 + threadIdx.x * 4;
+    if (c >= n + 2) continue;
     int32_t xv[4], yv[4] = {0, 0, 0, 0};
     ld4(X, rr * L.px + c, xv, true);
     if (HASY) ld4(Y, rr * L.py + c, yv, true);
     int64_t out[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = E.apply(xv[k], yv[k]);
+    for (int k = 0; k < 4; ++k) out[k] = E.put(xv[k], yv[k], true);
     if (PASS != kQ1) st4(Z, rr * L.pz + c, out);
   }
   E.finish();
@@ -38,10 +48,8 @@ __global__ __launch_bounds__(kBlock) void k_point(const PointLaunch L) {
 
 template <typename TX, typename TY, typename TZ, int PASS, bool HASY>
 static hipError_t point_go(const PointLaunch& L, hipStream_t s) {
-  const int64_t rows = L.ndim == 3 ? L.n * L.n : L.n;
-  const int64_t blocks = rows * ((L.n + 2 + 1023) / 1024);
-  hipLaunchKernelGGL((k_point<TX, TY, TZ, PASS, HASY>), dim3((unsigned)blocks), dim3(kBlock), 0,
-                     s, L);
+  hipLaunchKernelGGL((k_point<TX, TY, TZ, PASS, HASY>), dim3(grid_for(row_items(L.n, L.ndim))),
+                     dim3(kBlock), 0, s, L);
   return hipGetLastError();
 }
 
@@ -84,38 +92,39 @@ __device__ __forceinline__ bool f64_parts(double x, int64_t& z, int64_t& e, bool
 __global__ __launch_bounds__(kBlock) void k_f64_nu(const ConvertLaunch L) {
   const int64_t n = L.n, side = n + 2;
   const int64_t nchunk = (side + 1023) / 1024;
-  const int64_t rr = interior_row(blockIdx.x / nchunk, n, L.ndim);
-  const int64_t c0 = (int64_t)(blockIdx.x % nchunk) * 1024 + threadIdx.x * 4;
+  const int64_t items = row_items(n, L.ndim);
   int64_t best = INT64_MIN;
   bool bad = false;
-  for (int k = 0; k < 4; ++k) {
-    const int64_t c = c0 + k;
-    if (c < 1 || c > n) continue;
-    int64_t z, e;
-    bool fin;
-    if (f64_parts(L.src[rr * side + c], z, e, fin)) {
-      const int64_t nu = msb64(z) + e;
-      best = nu > best ? nu : best;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t rr = interior_row(it / nchunk, n, L.ndim);
+    const int64_t c0 = (it % nchunk) * 1024 + threadIdx.x * 4;
+    for (int k = 0; k < 4; ++k) {
+      const int64_t c = c0 + k;
+      if (c < 1 || c > n) continue;
+      int64_t z, e;
+      bool fin;
+      if (f64_parts(L.src[rr * side + c], z, e, fin)) {
+        const int64_t nu = msb64(z) + e;
+        best = nu > best ? nu : best;
+      }
+      bad |= !fin;
     }
-    bad |= !fin;
   }
   if (bad) atomicOr((unsigned long long*)&L.meta[kMetaFlags], 1ull);
-  // block / grid max into the scratch slot; the last block publishes it
+  // grid max of nu into the accumulator sets; the last block publishes it
+  // in kMetaMu (INT64_MIN when every value is zero)
   __shared__ int64_t s_red[kBlock / 64];
-  best = wave_max(best);
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = best;
-  __syncthreads();
+  const int64_t b = block_max(best, s_red);
   if (threadIdx.x == 0) {
-    int64_t b = s_red[0];
-    for (int i = 1; i < kBlock / 64; ++i) b = s_red[i] > b ? s_red[i] : b;
-    if (b != INT64_MIN) atomicMax((long long*)&L.meta[kMetaAccMax], (long long)b);
-    __threadfence();
-    unsigned long long t = atomicAdd((unsigned long long*)&L.meta[kMetaTicket], 1ull);
-    if (t == (unsigned long long)gridDim.x - 1) {
-      __threadfence();
-      L.meta[kMetaMu] = atomic_load64(&L.meta[kMetaAccMax]);  // INT64_MIN: all zero
-      atomic_store64(&L.meta[kMetaAccMax], INT64_MIN);
-      atomic_store64(&L.meta[kMetaTicket], 0);
+    int64_t* set = acc_set(L.meta);
+    if (take_ticket(L.meta, amax(&set[kAccMax], b))) {
+      int64_t mx = INT64_MIN;
+      for (int k = 0; k < kSets; ++k) {
+        const int64_t a = axch(&L.meta[kSetBase + kSetStride * k + kAccMax], INT64_MIN);
+        mx = a > mx ? a : mx;
+      }
+      axch(&L.meta[kMetaTicket], 0);
+      L.meta[kMetaMu] = mx;
     }
   }
 }
@@ -125,13 +134,15 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_f64_conv(const ConvertLaunch L) {
   const int64_t n = L.n, side = n + 2;
   const int64_t nchunk = (side + 1023) / 1024;
-  const int64_t rr = interior_row(blockIdx.x / nchunk, n, L.ndim);
-  const int64_t c0 = (int64_t)(blockIdx.x % nchunk) * 1024 + threadIdx.x * 4;
+  const int64_t items = row_items(n, L.ndim);
   const int64_t numax = L.meta[kMetaMu];
   const bool allzero = numax == INT64_MIN;
   const int64_t eq = allzero ? 1 - L.w : numax - L.w;     // exponent before scaling
   int64_t tmax = 0, tmin = 0;
-  if (c0 < side) {
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t rr = interior_row(it / nchunk, n, L.ndim);
+    const int64_t c0 = (it % nchunk) * 1024 + threadIdx.x * 4;
+    if (c0 >= side) continue;
     int64_t out[4];
     for (int k = 0; k < 4; ++k) {
       const int64_t c = c0 + k;
@@ -152,8 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_f64_conv(const ConvertLaunch L) {
 }
 
 hipError_t launch_from_f64(const ConvertLaunch& L, hipStream_t s) {
-  const int64_t rows = L.ndim == 3 ? L.n * L.n : L.n;
-  const int64_t blocks = rows * ((L.n + 2 + 1023) / 1024);
+  const unsigned blocks = grid_for(row_items(L.n, L.ndim));
   hipLaunchKernelGGL(k_f64_nu, dim3((unsigned)blocks), dim3(kBlock), 0, s, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -200,9 +210,10 @@ __global__ void k_meta_init(int64_t* m, int64_t exp, int full) {
   const int i = threadIdx.x;
   if (i >= kMetaSlots) return;
   int64_t v = 0;
-  if (i == kMetaAccMax) v = INT64_MIN;
-  else if (i == kMetaAccMin) v = INT64_MAX;
-  else if (i < 8) {
+  if (i >= kSetBase) {
+    const int f = (i - kSetBase) % kSetStride;
+    v = f == kAccMax ? INT64_MIN : (f == kAccMin ? INT64_MAX : 0);
+  } else if (i < kMetaTicket) {
     if (!full) return;
     v = i == kMetaExp ? exp : (i == kMetaMu ? 1 : 0);
   }
@@ -217,12 +228,12 @@ hipError_t launch_init(void* mant, size_t bytes, int64_t* meta, int64_t exp, hip
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(64), 0, s, meta, exp, 1);
+  hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(kMetaSlots), 0, s, meta, exp, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_meta_reset(int64_t* meta, hipStream_t s) {
-  hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(64), 0, s, meta, (int64_t)0, 0);
+  hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(kMetaSlots), 0, s, meta, (int64_t)0, 0);
   return hipGetLastError();
 }
 
@@ -232,10 +243,12 @@ template <typename TX, typename TY>
 __global__ __launch_bounds__(kBlock) void k_dot(const DotLaunch L) {
   const int64_t n = L.n;
   const int64_t nchunk = (n + 2 + 1023) / 1024;
-  const int64_t rr = interior_row(blockIdx.x / nchunk, n, L.ndim);
-  const int64_t c = (int64_t)(blockIdx.x % nchunk) * 1024 + threadIdx.x * 4;
+  const int64_t items = row_items(n, L.ndim);
   __int128 acc = 0;
-  if (c < n + 2) {
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t rr = interior_row(it / nchunk, n, L.ndim);
+    const int64_t c = (it % nchunk) * 1024 + threadIdx.x * 4;
+    if (c >= n + 2) continue;
     int32_t xv[4], yv[4];
     ld4(static_cast<const TX*>(L.x), rr * L.px + c, xv, true);
     ld4(static_cast<const TY*>(L.y), rr * L.py + c, yv, true);
@@ -259,31 +272,28 @@ __global__ __launch_bounds__(kBlock) void k_dot(const DotLaunch L) {
   if (threadIdx.x == 0) {
     int64_t b0 = 0, b1 = 0, b2 = 0;
     for (int i = 0; i < kBlock / 64; ++i) { b0 += s_red[0][i]; b1 += s_red[1][i]; b2 += s_red[2][i]; }
+    // limbs go to accumulator sets laid out like a block's metadata scratch
     int64_t* o = L.out;
-    atomicAdd((unsigned long long*)&o[3], (unsigned long long)b0);
-    atomicAdd((unsigned long long*)&o[4], (unsigned long long)b1);
-    atomicAdd((unsigned long long*)&o[5], (unsigned long long)b2);
-    __threadfence();
-    unsigned long long t = atomicAdd((unsigned long long*)&o[6], 1ull);
-    if (t == (unsigned long long)gridDim.x - 1) {
-      __threadfence();
-      const __int128 v = (__int128)(unsigned __int128)(uint64_t)atomic_load64(&o[3]) +
-                         ((__int128)(unsigned __int128)(uint64_t)atomic_load64(&o[4]) << 32) +
-                         ((__int128)atomic_load64(&o[5]) << 64);
+    int64_t* set = acc_set(o);
+    const int64_t r = aadd(&set[0], b0) ^ aadd(&set[1], b1) ^ aadd(&set[2], b2);
+    if (take_ticket(o, r)) {
+      __int128 v = 0;
+      for (int k = 0; k < kSets; ++k) {
+        int64_t* sk = o + kSetBase + kSetStride * k;
+        v += (__int128)(unsigned __int128)(uint64_t)axch(&sk[0], 0);
+        v += (__int128)(unsigned __int128)(uint64_t)axch(&sk[1], 0) << 32;
+        v += (__int128)axch(&sk[2], 0) << 64;
+      }
+      axch(&o[kMetaTicket], 0);
       o[0] = (int64_t)(uint64_t)(unsigned __int128)v;
       o[1] = (int64_t)(v >> 64);
       o[2] = L.x_meta[kMetaExp] + L.y_meta[kMetaExp];
-      atomic_store64(&o[3], 0);
-      atomic_store64(&o[4], 0);
-      atomic_store64(&o[5], 0);
-      atomic_store64(&o[6], 0);
     }
   }
 }
 
 hipError_t launch_dot(const DotLaunch& L, hipStream_t s) {
-  const int64_t rows = L.ndim == 3 ? L.n * L.n : L.n;
-  const int64_t blocks = rows * ((L.n + 2 + 1023) / 1024);
+  const unsigned blocks = grid_for(row_items(L.n, L.ndim));
   return with_type(L.xbits, [&](auto tx) {
     return with_type(L.ybits, [&](auto ty) {
       hipLaunchKernelGGL((k_dot<decltype(tx), decltype(ty)>), dim3((unsigned)blocks), dim3(kBlock),

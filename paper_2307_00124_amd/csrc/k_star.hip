@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_star2d(const StarLaunch L) {
         else
           g = (int64_t)(t0 * cur[k] + txm * xl + txp * xr + tym * up[k] + typ * dn[k]);
         const int64_t col = c + k;
-        out[k] = (col >= 1 && col <= n) ? E.apply(g, yv[k]) : 0;
+        out[k] = E.put(g, yv[k], col >= 1 && col <= n);
       }
       if (PASS != kQ1 && act_z) st4(Z, r * pz + c, out);
 #pragma unroll
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_star3d(const StarLaunch L) {
                           (int64_t)tym * ym[k] + (int64_t)typ * yp[k] +
                           (int64_t)tzm * zm[k] + (int64_t)tzp * zp[k];
         const int64_t col = c + k;
-        out[k] = (col >= 1 && col <= n) ? E.apply(g, yv[k]) : 0;
+        out[k] = E.put(g, yv[k], col >= 1 && col <= n);
       }
       if (PASS != kQ1 && act_z) st4(Z, row * pz + c, out);
 #pragma unroll

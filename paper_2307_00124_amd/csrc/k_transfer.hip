@@ -15,23 +15,25 @@ __device__ __forceinline__ int tap_index(const int (&o)[3]) {
   return ND == 2 ? (o[1] + 1) * 3 + (o[2] + 1) : ((o[0] + 1) * 3 + (o[1] + 1)) * 3 + (o[2] + 1);
 }
 
-// one coarse output point per thread; block = one run of 256 points of a
-// coarse interior row (rows flattened into blockIdx.x)
+// one coarse output point per thread; work items: (output row, run of 256 points) pairs, grid-strided over at
+// most kMaxBlocks blocks
 template <int ND, typename TX, typename TY, typename TZ, int PASS, bool HASY>
 __global__ __launch_bounds__(kBlock) void k_restrict(const TransferLaunch L) {
   const int64_t nc = L.n_out;
   const int64_t sf = L.n_in + 2, sc = nc + 2;
   const int64_t nchunk = (nc + kBlock - 1) / kBlock;
-  const int64_t row = blockIdx.x / nchunk;                 // 0 .. nc^(ND-1) - 1
-  const int64_t xc = (int64_t)(blockIdx.x % nchunk) * kBlock + threadIdx.x + 1;
-  int64_t zc = 0, yc;
-  if (ND == 3) { zc = row / nc + 1; yc = row % nc + 1; } else { yc = row + 1; }
+  const int64_t items = (ND == 3 ? nc * nc : nc) * nchunk;
   const TX* X = static_cast<const TX*>(L.x);
   const TY* Y = static_cast<const TY*>(L.y);
   TZ* Z = static_cast<TZ*>(L.z);
   Epi<PASS, HASY> E;
   E.init(L.op);
-  if (xc <= nc) {
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t row = it / nchunk;                       // 0 .. nc^(ND-1) - 1
+    const int64_t xc = (it % nchunk) * kBlock + threadIdx.x + 1;
+    int64_t zc = 0, yc;
+    if (ND == 3) { zc = row / nc + 1; yc = row % nc + 1; } else { yc = row + 1; }
+    if (xc > nc) continue;
     int64_t g = 0;
     int o[3];
     for (o[0] = (ND == 3 ? -1 : 0); o[0] <= (ND == 3 ? 1 : 0); ++o[0])
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const TransferLaunch L) {
       }
     const int64_t crow = ND == 3 ? zc * sc + yc : yc;
     const int64_t yv = HASY ? (int64_t)Y[crow * L.py + xc] : 0;
-    const int64_t v = E.apply(g, yv);
+    const int64_t v = E.put(g, yv, true);
     if (PASS != kQ1) Z[crow * L.pz + xc] = (TZ)v;
   }
   E.finish();
@@ -58,16 +60,18 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const TransferLaunch L) {
   const int64_t sf = nf + 2, sc = nc + 2;
   const int64_t cells = nc + 1;                               // coarse cells per dim
   const int64_t nchunk = (cells + kBlock - 1) / kBlock;
-  const int64_t row = blockIdx.x / nchunk;
-  const int64_t cx = (int64_t)(blockIdx.x % nchunk) * kBlock + threadIdx.x;
-  int64_t cz = 0, cy;
-  if (ND == 3) { cz = row / cells; cy = row % cells; } else { cy = row; }
+  const int64_t items = (ND == 3 ? cells * cells : cells) * nchunk;
   const TX* X = static_cast<const TX*>(L.x);
   const TY* Y = static_cast<const TY*>(L.y);
   TZ* Z = static_cast<TZ*>(L.z);
   Epi<PASS, HASY> E;
   E.init(L.op);
-  if (cx < cells) {
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t row = it / nchunk;
+    const int64_t cx = (it % nchunk) * kBlock + threadIdx.x;
+    int64_t cz = 0, cy;
+    if (ND == 3) { cz = row / cells; cy = row % cells; } else { cy = row; }
+    if (cx >= cells) continue;
     int64_t cv[2][2][2];
 #pragma unroll
     for (int ez = 0; ez < (ND == 3 ? 2 : 1); ++ez)
@@ -109,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const TransferLaunch L) {
             }
           }
           const int64_t yv = HASY ? (int64_t)Y[frow * L.py + fx] : 0;
-          outv[dx] = E.apply(g, yv);
+          outv[dx] = E.put(g, yv, true);
           if (PASS != kQ1) Z[frow * L.pz + fx] = (TZ)outv[dx];
         }
       }
@@ -122,15 +126,17 @@ static hipError_t transfer_go(const TransferLaunch& L, hipStream_t s) {
   if (L.kind == 1) {
     const int64_t nc = L.n_out;
     const int64_t rows = ND == 3 ? nc * nc : nc;
-    const int64_t blocks = rows * ((nc + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_restrict<ND, TX, TY, TZ, PASS, HASY>), dim3((unsigned)blocks),
-                       dim3(kBlock), 0, s, L);
+    const int64_t items = rows * ((nc + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_restrict<ND, TX, TY, TZ, PASS, HASY>),
+                       dim3((unsigned)(items < kMaxBlocks ? items : kMaxBlocks)), dim3(kBlock), 0,
+                       s, L);
   } else {
     const int64_t cells = L.n_in + 1;
     const int64_t rows = ND == 3 ? cells * cells : cells;
-    const int64_t blocks = rows * ((cells + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_prolong<ND, TX, TY, TZ, PASS, HASY>), dim3((unsigned)blocks),
-                       dim3(kBlock), 0, s, L);
+    const int64_t items = rows * ((cells + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_prolong<ND, TX, TY, TZ, PASS, HASY>),
+                       dim3((unsigned)(items < kMaxBlocks ? items : kMaxBlocks)), dim3(kBlock), 0,
+                       s, L);
   }
   return hipGetLastError();
 }

@@ -17,15 +17,22 @@ namespace bfpk {
 
 static thread_local std::string g_last_error;
 
-// Launch-shape tuning (rows or planes marched by one wave in the star
-// kernels, chosen per grid size): rows = 1 below the threshold n, then
-// `rows_large` (latency-bound small grids want many independent waves,
-// large grids want longer marches that reuse the line window).
-static int g_star2d_rows_large = 16, g_star2d_small_n = 512;
+// Launch-shape tuning of the star kernels: rows (2D) or planes (3D) one
+// wave marches. Measured on MI355X: a march pays about one memory latency
+// per 4-line batch, so longer marches win only while the grid still offers
+// ~1-2 waves per SIMD. The default picks rows = n^2 / 2^18 (2D), clamped to
+// [1, 64] and rounded down to a power of two; the tuning keys override it.
+static int g_star2d_rows_large = 0, g_star2d_small_n = 0;
 static int g_star3d_rows_large = 16, g_star3d_small_n = 64;
 
 static int star_rows(int ndim, int64_t n) {
-  if (ndim == 2) return n < g_star2d_small_n ? 1 : g_star2d_rows_large;
+  if (ndim == 2) {
+    if (g_star2d_rows_large > 0) return n < g_star2d_small_n ? 1 : g_star2d_rows_large;
+    int64_t r = n * n / (1 << 18);
+    int rows = 1;
+    while (rows * 2 <= r && rows < 64) rows *= 2;
+    return rows;
+  }
   return n < g_star3d_small_n ? 1 : g_star3d_rows_large;
 }
 
@@ -194,10 +201,32 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
   bool wide = true;
   if ((rc = check_budget(A, x, al->m, y, be->m, &wide))) return rc;
 
+  // alpha * (A x) = (alpha_m A) x: fold alpha's mantissa into the taps when
+  // every product fits the 24-bit tap range, so the kernels skip a 64-bit
+  // multiply per point (the exact value is unchanged)
+  int32_t taps[27];
+  int64_t am = al->m;
+  bool fold = true;
+  for (int i = 0; i < 27; ++i) {
+    const int64_t t = (int64_t)A->taps[i] * al->m;
+    if (t < -(1 << 23) || t >= (1 << 23)) fold = false;
+  }
+  for (int i = 0; i < 27; ++i) taps[i] = fold ? (int32_t)(A->taps[i] * al->m) : A->taps[i];
+  if (fold) am = 1;
+  bfp_stencil Af = *A;
+  for (int i = 0; i < 27; ++i) Af.taps[i] = taps[i];
+  A = &Af;
+  {
+    // int32 accumulation of the (folded) stencil sum only when it cannot overflow
+    long double gb = 0;
+    for (int i = 0; i < 27; ++i) gb += std::abs((long double)taps[i]);
+    wide = !(gb * ldexpl(1.0L, x->w - 1) < ldexpl(1.0L, 31));
+  }
+
   OpArgs op{};
   fill_common(&op, w_out, x, y, z);
   op.e_A = A->exp;
-  op.alpha_m = al->m;
+  op.alpha_m = am;
   op.alpha_e = al->exp;
   op.beta_m = y ? be->m : 0;
   op.beta_e = y ? be->exp : 0;

@@ -15,19 +15,29 @@
 #include "device.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace bfpk {
 
 constexpr int kQ1 = 1;   // template flag: first qcomp pass
 constexpr int kOut = 0;  // template flag: output-writing pass (mode chosen at run time)
 
+// Branch-free loads: an out-of-range request reads element 0 of the block
+// (always valid) and yields zeros, so a batch of loads stays one straight
+// run of instructions with no wait between them.
 template <typename T>
 __device__ __forceinline__ void ld4(const T* base, int64_t off, int32_t (&v)[4], bool ok) {
-  if (ok) {
-    Q4<T> q = *reinterpret_cast<const Q4<T>*>(base + off);
-    v[0] = q.v[0]; v[1] = q.v[1]; v[2] = q.v[2]; v[3] = q.v[3];
-  } else {
-    v[0] = v[1] = v[2] = v[3] = 0;
-  }
+  const Q4<T> q = *reinterpret_cast<const Q4<T>*>(base + (ok ? off : 0));
+  v[0] = ok ? (int32_t)q.v[0] : 0;
+  v[1] = ok ? (int32_t)q.v[1] : 0;
+  v[2] = ok ? (int32_t)q.v[2] : 0;
+  v[3] = ok ? (int32_t)q.v[3] : 0;
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t ld1(const T* base, int64_t off, bool ok) {
+  const T q = base[ok ? off : 0];
+  return ok ? (int32_t)q : 0;
 }
 
 template <typename T>
@@ -35,6 +45,19 @@ __device__ __forceinline__ void st4(T* base, int64_t off, const int64_t (&v)[4])
   Q4<T> q;
   q.v[0] = (T)v[0]; q.v[1] = (T)v[1]; q.v[2] = (T)v[2]; q.v[3] = (T)v[3];
   *reinterpret_cast<Q4<T>*>(base + off) = q;
+}
+
+// Epilogue variants chosen once per launch, outside the loops:
+//   kVarFastA1 — fast path and alpha = 1 (a = g, no multiply),
+//   kVarFast   — fast path, general alpha,
+//   kVarGen    — exact generic combine.
+constexpr int kVarGen = 0, kVarFast = 1, kVarFastA1 = 2;
+
+template <typename E, typename F>
+__device__ __forceinline__ void with_fast(const E& e, F&& body) {
+  if (e.fast && e.alpha_m == 1) body(std::integral_constant<int, kVarFastA1>());
+  else if (e.fast) body(std::integral_constant<int, kVarFast>());
+  else body(std::integral_constant<int, kVarGen>());
 }
 
 template <int PASS, bool HASY>
@@ -48,7 +71,7 @@ struct Epi {
   // with no possible overflow (|hi|, |lo| < 2^61)
   int fast;
   int fswap, fd, fs;
-  int64_t tsat;
+  int32_t tsat;
   int32_t tmax, tmin;
   int64_t tmu;
   int64_t* zm;
@@ -82,19 +105,20 @@ struct Epi {
     tmu = 1;
   }
 
-  __device__ __forceinline__ int64_t mul_a(int64_t g) const {
-    return alpha_m == 1 ? g : (alpha_m == -1 ? -g : alpha_m * g);
-  }
-  __device__ __forceinline__ int64_t mul_b(int64_t y) const {
-    return beta_m == 1 ? y : (beta_m == -1 ? -y : beta_m * y);
+  __device__ __forceinline__ int64_t mul_a(int64_t g) const { return alpha_m * g; }
+  // |beta| < 2^31 (checked on the host): one 32 x 32 -> 64-bit multiply
+  __device__ __forceinline__ int64_t mul_b(int32_t y) const {
+    return (int64_t)(int32_t)beta_m * (int64_t)y;
   }
 
-  // floor of the exact result at the output exponent (+-2^62 when beyond)
-  __device__ __forceinline__ int64_t value(int64_t g, int64_t yv) const {
-    const int64_t a = mul_a(g);
-    if (!HASY) return fast ? (a >> fs) : scale1(a, R.sa);
+  // floor of the exact result at the output exponent (+-2^62 when beyond);
+  // VAR must match the launch (the kernels choose it once via with_fast)
+  template <int VAR>
+  __device__ __forceinline__ int64_t value(int64_t g, int32_t yv) const {
+    const int64_t a = VAR == kVarFastA1 ? g : mul_a(g);
+    if (!HASY) return VAR != kVarGen ? (a >> fs) : scale1(a, R.sa);
     const int64_t b = mul_b(yv);
-    if (fast) {
+    if (VAR != kVarGen) {
       const int64_t h = fswap ? b : a, l = fswap ? a : b;
       return (h + (l >> fd)) >> fs;
     }
@@ -103,7 +127,8 @@ struct Epi {
 
   // Process one output point (inside = interior point of the output grid);
   // returns its mantissa, 0 outside or in the first qcomp pass.
-  __device__ __forceinline__ int64_t put(int64_t g, int64_t yv, bool inside) {
+  template <int VAR>
+  __device__ __forceinline__ int64_t put(int64_t g, int32_t yv, bool inside) {
     if (PASS == kQ1) {
       const int64_t a = mul_a(g);
       int m;
@@ -117,7 +142,7 @@ struct Epi {
       tmu = m > tmu ? m : tmu;
       return 0;
     }
-    const int64_t v = value(g, yv);
+    const int64_t v = value<VAR>(g, yv);
     const int64_t c = v < lo ? lo : (v > hi ? hi : v);
     tsat += (inside && c != v) ? 1 : 0;
     const int32_t r = inside ? (int32_t)c : 0;

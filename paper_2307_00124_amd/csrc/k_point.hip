@@ -31,18 +31,21 @@ __global__ __launch_bounds__(kBlock) void k_point(const PointLaunch L) {
   TZ* Z = static_cast<TZ*>(L.z);
   Epi<PASS, HASY> E;
   E.init(L.op);
-  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-    const int64_t rr = interior_row(it / nchunk, n, L.ndim);
-    const int64_t c = (it % nchunk) * 1024 + threadIdx.x * 4;
-    if (c >= n + 2) continue;
-    int32_t xv[4], yv[4] = {0, 0, 0, 0};
-    ld4(X, rr * L.px + c, xv, true);
-    if (HASY) ld4(Y, rr * L.py + c, yv, true);
-    int64_t out[4];
+  with_fast(E, [&](auto fast_tag) {
+    constexpr int VAR = decltype(fast_tag)::value;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+      const int64_t rr = interior_row(it / nchunk, n, L.ndim);
+      const int64_t c = (it % nchunk) * 1024 + threadIdx.x * 4;
+      if (c >= n + 2) continue;
+      int32_t xv[4], yv[4] = {0, 0, 0, 0};
+      ld4(X, rr * L.px + c, xv, true);
+      if (HASY) ld4(Y, rr * L.py + c, yv, true);
+      int64_t out[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = E.put(xv[k], yv[k], true);
-    if (PASS != kQ1) st4(Z, rr * L.pz + c, out);
-  }
+      for (int k = 0; k < 4; ++k) out[k] = E.template put<VAR>(xv[k], yv[k], true);
+      if (PASS != kQ1) st4(Z, rr * L.pz + c, out);
+    }
+  });
   E.finish();
 }
 

@@ -28,6 +28,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const TransferLaunch L) {
   TZ* Z = static_cast<TZ*>(L.z);
   Epi<PASS, HASY> E;
   E.init(L.op);
+  with_fast(E, [&](auto fast_tag) {
+  constexpr int VAR = decltype(fast_tag)::value;
   for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
     const int64_t row = it / nchunk;                       // 0 .. nc^(ND-1) - 1
     const int64_t xc = (it % nchunk) * kBlock + threadIdx.x + 1;
@@ -48,9 +50,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const TransferLaunch L) {
       }
     const int64_t crow = ND == 3 ? zc * sc + yc : yc;
     const int64_t yv = HASY ? (int64_t)Y[crow * L.py + xc] : 0;
-    const int64_t v = E.put(g, yv, true);
+    const int64_t v = E.template put<VAR>(g, yv, true);
     if (PASS != kQ1) Z[crow * L.pz + xc] = (TZ)v;
   }
+  });
   E.finish();
 }
 
@@ -66,6 +69,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const TransferLaunch L) {
   TZ* Z = static_cast<TZ*>(L.z);
   Epi<PASS, HASY> E;
   E.init(L.op);
+  with_fast(E, [&](auto fast_tag) {
+  constexpr int VAR = decltype(fast_tag)::value;
   for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
     const int64_t row = it / nchunk;
     const int64_t cx = (it % nchunk) * kBlock + threadIdx.x;
@@ -113,11 +118,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const TransferLaunch L) {
             }
           }
           const int64_t yv = HASY ? (int64_t)Y[frow * L.py + fx] : 0;
-          outv[dx] = E.put(g, yv, true);
+          outv[dx] = E.template put<VAR>(g, yv, true);
           if (PASS != kQ1) Z[frow * L.pz + fx] = (TZ)outv[dx];
         }
       }
   }
+  });
   E.finish();
 }
 

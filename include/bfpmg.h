@@ -311,10 +311,13 @@ int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out);
  * the number of kernel launches (host-side counters).                     */
 int mg_counters(const mg_hierarchy* h, double* bytes, int64_t* launches);
 
-/* Launch-shape tuning of the star stencil kernels (process-wide; results
- * do not depend on it): "star2d_rows" / "star3d_rows" = rows or planes one
- * wave marches on large grids, "star2d_small_n" / "star3d_small_n" = grid
- * size below which every wave takes a single row.                        */
+/* Launch-shape tuning (process-wide; results do not depend on it):
+ * "star2d_rows" / "star3d_rows" = rows or planes one wave of the star
+ * stencil kernels marches on large grids, "star2d_small_n" /
+ * "star3d_small_n" = grid size below which every wave takes a single row
+ * (values >= 1); "exec_max_points" = largest grid (in interior points) whose
+ * level runs inside the one-workgroup coarse-level programs a hierarchy
+ * records at creation (0 = never; read by mg_hierarchy_bytes/create).     */
 int bfp_tuning_set(const char* key, int value);
 
 /* Human-readable description of the last error on this thread.           */

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbfpmg.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "mg.cpp", "k_star.hip", "k_transfer.hip", "k_point.hip"]
+SOURCES = ["api.cpp", "mg.cpp", "k_star.hip", "k_transfer.hip", "k_point.hip", "k_exec.hip"]
 ARCH = os.environ.get("BFPMG_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

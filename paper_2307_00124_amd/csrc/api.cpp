@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/bfpmg.h"
 #include "api_internal.hpp"
@@ -24,6 +25,38 @@ static thread_local std::string g_last_error;
 // [1, 64] and rounded down to a power of two; the tuning keys override it.
 static int g_star2d_rows_large = 0, g_star2d_small_n = 0;
 static int g_star3d_rows_large = 16, g_star3d_small_n = 64;
+
+// Coarse-level executor: programs are recorded for the levels whose grids
+// hold at most this many points (0 disables the executor).
+static int g_exec_max_points = 4096;
+
+int exec_max_points() { return g_exec_max_points; }
+
+// While a sink is installed (on this host thread), the operations append
+// their launch descriptions to it instead of launching.
+static thread_local std::vector<ExecOp>* g_rec = nullptr;
+
+void record_into(std::vector<ExecOp>* sink) { g_rec = sink; }
+bool recording() { return g_rec != nullptr; }
+
+static int64_t out_n(const StarLaunch& l) { return l.n; }
+static int64_t out_n(const TransferLaunch& l) { return l.n_out; }
+static int64_t out_n(const PointLaunch& l) { return l.n; }
+static void put_launch(ExecOp& e, const StarLaunch& l) { e.kind = kExStar; e.u.star = l; }
+static void put_launch(ExecOp& e, const TransferLaunch& l) { e.kind = kExTransfer; e.u.tr = l; }
+static void put_launch(ExecOp& e, const PointLaunch& l) { e.kind = kExPoint; e.u.pt = l; }
+
+template <typename L>
+static int record(const L& launch, int exec_mode) {
+  if (out_n(launch) >= kExecMaxN)
+    return fail(BFP_ESHAPE, "grid too large for the coarse-level executor");
+  ExecOp e;
+  std::memset(&e, 0, sizeof e);
+  put_launch(e, launch);
+  e.mode = exec_mode;
+  g_rec->push_back(e);
+  return BFP_OK;
+}
 
 static int star_rows(int ndim, int64_t n) {
   if (ndim == 2) {
@@ -163,6 +196,7 @@ static void fill_common(OpArgs* op, int w_out, const bfp_vec* x, const bfp_vec* 
 // mu* pass followed by the output pass.
 template <typename L, typename F>
 static int run_modes(L& launch, int mode, F&& go) {
+  if (g_rec) return record(launch, mode == BFP_SATURATE ? kModeSat : kExModeQ);
   if (mode == BFP_SATURATE) {
     launch.op.mode = kModeSat;
     return hip_check(go(launch), "kernel launch");
@@ -319,6 +353,7 @@ int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta
   L.zbits = z->storage_bits;
   if (forced_mode == kModeNormMeta || forced_mode == kModeAssign) {
     L.op.mode = forced_mode;
+    if (g_rec) return record(L, forced_mode);
     return hip_check(launch_point(L, s), "pointwise launch");
   }
   if (mode != BFP_NORMALIZE && mode != BFP_SATURATE) return fail(BFP_EINVAL, "bad mode %d", mode);
@@ -349,6 +384,14 @@ int bfp_vec_init(const bfp_vec* v, void* stream) {
   int rc = check_vec(v, "v");
   if (rc) return rc;
   const size_t bytes = (size_t)(v->pitch * rows_for(v->ndim, v->n) * (v->storage_bits / 8));
+  if (g_rec) {
+    ExecOp e;
+    std::memset(&e, 0, sizeof e);
+    e.kind = kExZero;
+    e.u.zero = ZeroOp{v->mant, v->meta, (int64_t)bytes, (int64_t)(1 - v->w)};
+    g_rec->push_back(e);
+    return BFP_OK;
+  }
   return hip_check(launch_init(v->mant, bytes, v->meta, 1 - v->w, (hipStream_t)stream),
                    "bfp_vec_init");
 }
@@ -446,8 +489,10 @@ int bfp_saturate_truncate(const bfp_vec* in, int w_out, const bfp_gamma* gamma, 
 
 int bfp_tuning_set(const char* key, int value) {
   if (!key) return fail(BFP_EINVAL, "key is NULL");
-  if (value < 1 || value > 1 << 20) return fail(BFP_EINVAL, "value out of range");
+  if (value < 0 || value > 1 << 20) return fail(BFP_EINVAL, "value out of range");
   const std::string k(key);
+  if (k == "exec_max_points") { g_exec_max_points = value; return BFP_OK; }
+  if (value < 1) return fail(BFP_EINVAL, "value out of range");
   if (k == "star2d_rows") g_star2d_rows_large = value;
   else if (k == "star2d_small_n") g_star2d_small_n = value;
   else if (k == "star3d_rows") g_star3d_rows_large = value;

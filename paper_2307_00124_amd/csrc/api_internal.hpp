@@ -6,6 +6,9 @@
 
 #include "../../include/bfpmg.h"
 #include "common.hpp"
+#include "kernels.hpp"
+
+#include <vector>
 
 namespace bfpk {
 
@@ -25,5 +28,13 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
 int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta,
                const bfp_vec* y, int w_out, int mode, const bfp_gamma* gamma, bfp_vec* z,
                hipStream_t s, int forced_mode);
+
+// Recording of coarse-level programs: while a sink is installed on the
+// calling thread, stencil_apply_impl, point_impl and bfp_vec_init append
+// ExecOps to it instead of launching kernels.
+void record_into(std::vector<ExecOp>* sink);
+bool recording();
+// grids of at most this many points run inside recorded programs (0: never)
+int exec_max_points();
 
 }  // namespace bfpk

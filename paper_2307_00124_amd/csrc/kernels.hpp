@@ -88,4 +88,34 @@ struct DotLaunch {
 };
 hipError_t launch_dot(const DotLaunch& L, hipStream_t s);
 
+// One recorded operation of a coarse-level program (see k_exec.hip): the
+// launch description the library would otherwise launch, and its mode.
+constexpr int kExStar = 1, kExTransfer = 2, kExPoint = 3, kExZero = 4;
+constexpr int kExModeQ = 9;   // both qcomp passes, executed back to back
+
+// bfp_vec_init inside a program: zero mantissas, exponent 1 - w
+struct ZeroOp {
+  void* mant;
+  int64_t* meta;
+  int64_t bytes;   // multiple of 16
+  int64_t exp;
+};
+
+struct ExecOp {
+  int kind;
+  int mode;   // kModeSat, kModeNormMeta, kModeAssign or kExModeQ
+  union {
+    StarLaunch star;
+    TransferLaunch tr;
+    PointLaunch pt;
+    ZeroOp zero;
+  } u;
+};
+
+// Run ops[0..count) in order inside one workgroup of kExecThreads threads;
+// every op works on grids of one dimension ndim with n_out < kExecMaxN.
+constexpr int kExecThreads = 1024;
+constexpr int kExecMaxN = 1024;
+hipError_t launch_exec(const ExecOp* ops_dev, int count, int ndim, hipStream_t s);
+
 }  // namespace bfpk

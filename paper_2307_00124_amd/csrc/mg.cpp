@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/bfpmg.h"
 #include "api_internal.hpp"
@@ -37,6 +38,14 @@ struct Level {
 
 }  // namespace
 
+// A recorded coarse-level program: ops in the arena, run by one launch of
+// the executor; `bytes` is the algorithmic traffic of the ops it stands for.
+struct Program {
+  ExecOp* ops;
+  int count;
+  double bytes;
+};
+
 struct mg_hierarchy {
   mg_params prm;
   Level lv[MG_MAX_LEVELS + 1];
@@ -44,6 +53,9 @@ struct mg_hierarchy {
   bfp_scalar vres;      // (2 c1 + 1) / 4 with the D-scaled c1, exact
   double bytes;
   int64_t launches;
+  int Lc;               // levels 1..Lc run inside the programs (0: none)
+  Program progV;        // V-cycle on level Lc from its restricted residual vr
+  Program progF;        // FMG on levels 1..Lc (from x_1 = 0)
 };
 
 namespace {
@@ -157,11 +169,22 @@ int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, int 
   return BFP_OK;
 }
 
+int run_program(mg_hierarchy* h, const Program& pg, hipStream_t s) {
+  int rc = hip_check(launch_exec(pg.ops, pg.count, h->prm.ndim, s), "coarse-level program");
+  if (rc) return rc;
+  h->bytes += pg.bytes;
+  h->launches += 1;
+  return BFP_OK;
+}
+
 // y = V(l, rin)
 int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
   Level& L = h->lv[l];
   const mg_params& p = h->prm;
   int rc;
+  if (!recording() && l == h->Lc && h->progV.count && rin.mant == L.vr.mant &&
+      rin.meta == L.vr.meta)
+    return run_program(h, h->progV, s);
   // relaxation from y = 0: y = c2 A r + c1 r
   if ((rc = op_stencil(h, &h->A, rin, &p.c2, &p.c1, &rin, L.y, mode_for(h, kRelax, false),
                        g_norm(rin, p.c1), s)))
@@ -223,6 +246,69 @@ int ir_iteration(mg_hierarchy* h, int l, const bfp_gamma* gres, bool first, bool
   return op_sub(h, L.x, L.y, L.x, mode_for(h, kIrCorr, false), g_sum(L.x, L.y), s);
 }
 
+// FMG levels lo..hi (lo = 1 starts from x_1 = 0)
+int fmg_levels(mg_hierarchy* h, int lo, int hi, hipStream_t s) {
+  const mg_params& p = h->prm;
+  int rc;
+  if (lo == 1) {
+    if ((rc = bfp_vec_init(&h->lv[1].x, s))) return rc;
+    h->launches += 2;
+  }
+  for (int l = lo; l <= hi; ++l) {
+    Level& L = h->lv[l];
+    if (l > 1) {
+      Level& C = h->lv[l - 1];
+      if ((rc = op_stencil(h, &h->P, C.x, &kOne, nullptr, nullptr, L.x,
+                           mode_for(h, kFmgProl, false), g_norm(C.x, kOne), s)))
+        return rc;
+    }
+    for (int i = 1; i <= p.N; ++i) {
+      bfp_gamma g = i > 1 ? g_norm(L.r, kOne)
+                          : (l > 1 ? g_norm(h->lv[l - 1].r, kOne) : g_norm(L.b, kOne));
+      if ((rc = ir_iteration(h, l, &g, i == 1, false, s))) return rc;
+    }
+  }
+  return BFP_OK;
+}
+
+// levels whose grids fit the coarse-level executor
+int exec_levels(const mg_params* p) {
+  const int64_t maxp = exec_max_points();
+  int lc = 0;
+  for (int j = 1; j <= p->L; ++j) {
+    const int64_t n = ((int64_t)1 << j) - 1;
+    const int64_t pts = p->ndim == 3 ? n * n * n : n * n;
+    if (pts > maxp || n >= kExecMaxN) break;
+    lc = j;
+  }
+  return lc;
+}
+
+// Record the coarse-level programs of a laid-out hierarchy (no device work):
+// the V-cycle on level Lc from vr and FMG on levels 1..Lc, through the same
+// code that otherwise launches each operation.
+int record_programs(mg_hierarchy* h, std::vector<ExecOp>* V, std::vector<ExecOp>* F,
+                    double* bytesV, double* bytesF) {
+  V->clear();
+  F->clear();
+  if (h->Lc == 0) return BFP_OK;
+  const double b0 = h->bytes;
+  const int64_t l0 = h->launches;
+  record_into(V);
+  int rc = vcycle(h, h->Lc, h->lv[h->Lc].vr, nullptr);
+  const double b1 = h->bytes;
+  if (!rc) {
+    record_into(F);
+    rc = fmg_levels(h, 1, h->Lc, nullptr);
+  }
+  record_into(nullptr);
+  *bytesV = b1 - b0;
+  *bytesF = h->bytes - b1;
+  h->bytes = b0;
+  h->launches = l0;
+  return rc;
+}
+
 int check_params(const mg_params* p) {
   if (!p) return fail(BFP_EINVAL, "params are NULL");
   if (p->ndim != 2 && p->ndim != 3) return fail(BFP_ESHAPE, "ndim must be 2 or 3");
@@ -244,8 +330,9 @@ int check_params(const mg_params* p) {
   return BFP_OK;
 }
 
-// Lay out (or only size) every level's blocks in the arena.
-size_t layout(mg_hierarchy* h, const mg_params* p, char* base) {
+// Lay out (or only size) every level's blocks in the arena, followed by
+// room for `nops` recorded operations.
+size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops) {
   size_t off = 0;
   const int mb = p->min_storage_bits;
   for (int j = 1; j <= p->L; ++j) {
@@ -271,7 +358,47 @@ size_t layout(mg_hierarchy* h, const mg_params* p, char* base) {
       off = align256(off + kMetaSlots * sizeof(int64_t));
     }
   }
+  h->progV.ops = base ? (ExecOp*)(base + off) : nullptr;
+  off = align256(off + nops * sizeof(ExecOp));
   return off;
+}
+
+// Host-side set-up shared by sizing and creation: stencils, the exact
+// (2 c1 + 1) / 4, the executor levels.
+int setup(mg_hierarchy* h, const mg_params* prm) {
+  h->prm = *prm;
+  make_stencils(prm->ndim, &h->A, &h->R, &h->P);
+  // (2 c1 + 1) / 4 exactly: c1 = m 2^e
+  const bfp_scalar c = prm->c1_gamma;
+  if (c.exp + 1 >= 0) {
+    h->vres.m = (c.m << (c.exp + 1)) + 1;
+    h->vres.exp = -2;
+  } else {
+    h->vres.m = c.m + ((int64_t)1 << (-(c.exp + 1)));
+    h->vres.exp = c.exp - 1;
+  }
+  h->vres.w = 24;
+  while (h->vres.m % 2 == 0) { h->vres.m /= 2; h->vres.exp += 1; }
+  if (h->vres.m >= (1 << 23)) return fail(BFP_EWIDTH, "(2 c1 + 1) / 4 needs more than 24 bits");
+  h->Lc = exec_levels(prm);
+  return BFP_OK;
+}
+
+// Number of recorded operations the hierarchy's programs hold: recorded
+// on a layout at a stand-in address, with no device work.
+int count_ops(const mg_params* prm, size_t* nops) {
+  mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
+  if (!h) return fail(BFP_ENOMEM, "host allocation failed");
+  int rc = setup(h, prm);
+  if (!rc) {
+    layout(h, prm, reinterpret_cast<char*>((uintptr_t)1 << 20), 0);
+    std::vector<ExecOp> V, F;
+    double bv, bf;
+    rc = record_programs(h, &V, &F, &bv, &bf);
+    *nops = V.size() + F.size();
+  }
+  delete h;
+  return rc;
 }
 
 }  // namespace
@@ -361,8 +488,10 @@ int mg_params_init(int ndim, int L, int w, int progressive, int nu1, int nu2, in
 
 size_t mg_hierarchy_bytes(const mg_params* prm) {
   if (check_params(prm)) return 0;
+  size_t nops = 0;
+  if (count_ops(prm, &nops)) return 0;
   mg_hierarchy tmp;
-  return layout(&tmp, prm, nullptr);
+  return layout(&tmp, prm, nullptr, nops);
 }
 
 int mg_hierarchy_create(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
@@ -371,36 +500,40 @@ int mg_hierarchy_create(const mg_params* prm, void* arena_dev, size_t bytes, voi
   if (rc) return rc;
   if (!out || !arena_dev) return fail(BFP_EINVAL, "NULL argument");
   if ((uintptr_t)arena_dev % 256) return fail(BFP_EINVAL, "arena must be 256-byte aligned");
+  size_t nops = 0;
+  if ((rc = count_ops(prm, &nops))) return rc;
   mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
   if (!h) return fail(BFP_ENOMEM, "host allocation failed");
-  h->prm = *prm;
-  const size_t need = layout(h, prm, nullptr);
+  if ((rc = setup(h, prm))) { delete h; return rc; }
+  const size_t need = layout(h, prm, nullptr, nops);
   if (bytes < need) {
     delete h;
     return fail(BFP_ENOMEM, "arena holds %zu bytes, the hierarchy needs %zu", bytes, need);
   }
-  layout(h, prm, static_cast<char*>(arena_dev));
-  make_stencils(prm->ndim, &h->A, &h->R, &h->P);
-  // (2 c1 + 1) / 4 exactly: c1 = m 2^e
-  const bfp_scalar c = prm->c1_gamma;
-  if (c.exp + 1 >= 0) {
-    h->vres.m = (c.m << (c.exp + 1)) + 1;
-    h->vres.exp = -2;
-  } else {
-    h->vres.m = c.m + ((int64_t)1 << (-(c.exp + 1)));
-    h->vres.exp = c.exp - 1;
-  }
-  h->vres.w = 24;
-  while (h->vres.m % 2 == 0) { h->vres.m /= 2; h->vres.exp += 1; }
-  if (h->vres.m >= (1 << 23)) {
-    delete h;
-    return fail(BFP_EWIDTH, "(2 c1 + 1) / 4 needs more than 24 bits");
-  }
+  layout(h, prm, static_cast<char*>(arena_dev), nops);
+  hipStream_t s = (hipStream_t)stream;
   for (int j = 1; j <= prm->L; ++j) {
     Level& L = h->lv[j];
     for (bfp_vec* v : {&L.x, &L.b, &L.r, &L.vr, &L.y, &L.s, &L.t}) {
       if ((rc = bfp_vec_init(v, stream))) { delete h; return rc; }
     }
+  }
+  std::vector<ExecOp> V, F;
+  if ((rc = record_programs(h, &V, &F, &h->progV.bytes, &h->progF.bytes))) { delete h; return rc; }
+  if (V.size() + F.size() != nops) {
+    delete h;
+    return fail(BFP_EINVAL, "recorded programs changed size (%zu vs %zu ops)", V.size() + F.size(), nops);
+  }
+  h->progV.count = (int)V.size();
+  h->progF.ops = h->progV.ops + V.size();
+  h->progF.count = (int)F.size();
+  if (nops) {
+    std::vector<ExecOp> all(V);
+    all.insert(all.end(), F.begin(), F.end());
+    rc = hip_check(hipMemcpyAsync(h->progV.ops, all.data(), nops * sizeof(ExecOp),
+                                  hipMemcpyHostToDevice, s), "program upload");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "program upload");
+    if (rc) { delete h; return rc; }
   }
   *out = h;
   return BFP_OK;
@@ -446,25 +579,13 @@ int mg_ir(mg_hierarchy* h, int level, int iters, void* stream) {
 int mg_fmg(mg_hierarchy* h, void* stream) {
   if (!h) return fail(BFP_EINVAL, "NULL hierarchy");
   hipStream_t s = (hipStream_t)stream;
-  const mg_params& p = h->prm;
   int rc;
-  if ((rc = bfp_vec_init(&h->lv[1].x, s))) return rc;
-  h->launches += 2;
-  for (int l = 1; l <= p.L; ++l) {
-    Level& L = h->lv[l];
-    if (l > 1) {
-      Level& C = h->lv[l - 1];
-      if ((rc = op_stencil(h, &h->P, C.x, &kOne, nullptr, nullptr, L.x,
-                           mode_for(h, kFmgProl, false), g_norm(C.x, kOne), s)))
-        return rc;
-    }
-    for (int i = 1; i <= p.N; ++i) {
-      bfp_gamma g = i > 1 ? g_norm(L.r, kOne)
-                          : (l > 1 ? g_norm(h->lv[l - 1].r, kOne) : g_norm(L.b, kOne));
-      if ((rc = ir_iteration(h, l, &g, i == 1, false, s))) return rc;
-    }
+  int lo = 1;
+  if (h->progF.count) {
+    if ((rc = run_program(h, h->progF, s))) return rc;
+    lo = h->Lc + 1;
   }
-  return BFP_OK;
+  return fmg_levels(h, lo, h->prm.L, s);
 }
 
 int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out) {

@@ -142,3 +142,50 @@ def test_full_size_fmg_coarse_levels_and_accuracy(w):
     disc = (fp64.kappa_h(L) - 1) * math.sqrt(float((us[1:-1, 1:-1] ** 2).sum()) * 2.0 ** (-2 * L))
     if w == 32:
         assert err <= 1.1 * disc, (err, disc)
+
+
+def _lib_hierarchy(ndim, L, w, progressive, policy, nu1, nu2, N, eta, exec_points):
+    P.bfp_tuning_set("exec_max_points", exec_points)
+    try:
+        p = P.mg_params_init(ndim, L, w, progressive, nu1, nu2, N, POLICY[policy], eta)
+        H = P.Hierarchy(p)
+    finally:
+        P.bfp_tuning_set("exec_max_points", 4096)
+    for j in range(1, L + 1):
+        H.set_rhs(j, torch.from_numpy(np.ascontiguousarray(W.manufactured_f(j, ndim))).cuda())
+    return H
+
+
+def _same_block(a, b, what):
+    assert torch.equal(a.mantissas(), b.mantissas()), what
+    assert a.host_meta()[:6] == b.host_meta()[:6], what
+
+
+@pytest.mark.parametrize("ndim,L,w,prog,policy,nu", [
+    (2, 8, 24, True, "nn_ir_first_q", (1, 0)), (2, 7, 32, False, "q", (2, 2)),
+    (2, 7, 12, True, "nn", (2, 1)), (3, 5, 20, True, "nn_ir_first_q", (1, 0)),
+    (3, 5, 32, False, "q", (2, 2))])
+def test_coarse_programs_match_launches(ndim, L, w, prog, policy, nu):
+    """FMG and IR with the coarse levels run by the one-workgroup executor
+    give the same blocks, bit for bit (mantissas and metadata), as with one
+    launch per operation."""
+    runs = []
+    for pts in (0, 4096):
+        H = _lib_hierarchy(ndim, L, w, prog, policy, nu[0], nu[1], 2, 23, pts)
+        H.fmg()
+        fmg_blocks = [(H.get_vec(j, 0).mantissas().clone(), H.get_vec(j, 0).host_meta()[:6],
+                       H.get_vec(j, 2).mantissas().clone(), H.get_vec(j, 2).host_meta()[:6])
+                      for j in range(1, L + 1)]
+        H.ir(L, 2)
+        runs.append((H, fmg_blocks))
+        torch.cuda.synchronize()
+    (H0, f0), (H1, f1) = runs
+    for j in range(1, L + 1):
+        for k in range(4):
+            a, b = f0[j - 1][k], f1[j - 1][k]
+            assert (torch.equal(a, b) if torch.is_tensor(a) else a == b), f"FMG level {j} item {k}"
+    _same_block(H0.get_vec(L, 0), H1.get_vec(L, 0), "x after IR")
+    _same_block(H0.get_vec(L, 2), H1.get_vec(L, 2), "r after IR")
+    b0, l0 = H0.counters()
+    b1, l1 = H1.counters()
+    assert abs(b0 - b1) <= 1e-9 * b0 and l1 < l0

@@ -101,7 +101,7 @@ def main():
 
     # ---------------------------------------------------------- main run --
     H = make(args.w)
-    xout = P.Vec(2, n, args.w, 32)
+    xout = P.Vec(2, n, H.get_vec(L, 0).w, 32)
     ms = timed(H, xout, args.steps, args.warmup)
     ratio = accuracy(xout)
     bytes_before, launches_before = H.counters()
@@ -138,7 +138,7 @@ def main():
     sweep = []
     for w in [int(s) for s in args.sweep.split(",") if s]:
         Hs = make(w)
-        xs = P.Vec(2, n, w, 32)
+        xs = P.Vec(2, n, Hs.get_vec(L, 0).w, 32)
         msw = timed(Hs, xs, 3, 1)
         sweep.append({"w": w, "ms": round(msw, 3), "dof_per_s": dof / (msw * 1e-3),
                       "err_over_disc": round(accuracy(xs), 4),

@@ -48,7 +48,8 @@ typedef enum {
   BFP_PENDING = 1      /* request not finished yet                             */
 } bfp_status;
 
-/* How an exact result z* is quantized to w_out bits.
+/* How an exact result z* is quantized to w_out bits (1 <= w_out <= the
+ * width w of the output block, which then holds w_out-bit mantissas).
  *  BFP_NORMALIZE — qcomp (Algorithm 1): normalized result, exact up to w_out
  *     bits: e_out = e_z* + mu* - w_out with mu* = max(1, max_i msb(z*_i)),
  *     m_i = floor(z*_i / 2^(mu* - w_out)). Independent of any estimate.

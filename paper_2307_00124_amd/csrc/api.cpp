@@ -163,6 +163,22 @@ static int tap(const bfp_stencil* A, int oz, int oy, int ox) {
                       : A->taps[(oy + 1) * 3 + (ox + 1)];
 }
 
+// bit bound k of a term: |m| * tsum * 2^(w-1) < 2^k bounds |m * sum t x| over
+// w-bit mantissas x (tsum = sum of |taps|, 1 for a pointwise term)
+static int term_bits(int64_t m, uint64_t tsum, int w) {
+  unsigned __int128 b = (unsigned __int128)(m < 0 ? -(unsigned __int128)m : (unsigned __int128)m) *
+                        tsum << (w - 1);
+  int k = 0;
+  while (b >> k) ++k;
+  return k;
+}
+
+static uint64_t tap_sum(const int32_t* t, int count) {
+  uint64_t s = 0;
+  for (int i = 0; i < count; ++i) s += (uint64_t)(t[i] < 0 ? -(int64_t)t[i] : t[i]);
+  return s;
+}
+
 // |alpha| * sum |t| * 2^(w-1) < 2^61 and |beta| 2^(wy-1) < 2^61
 static int check_budget(const bfp_stencil* A, const bfp_vec* x, int64_t alpha_m,
                         const bfp_vec* y, int64_t beta_m, bool* wide) {
@@ -216,8 +232,8 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
   if ((rc = check_vec(x, "x")) || (rc = check_vec(z, "z"))) return rc;
   if (y && (rc = check_vec(y, "y"))) return rc;
   if (mode != BFP_NORMALIZE && mode != BFP_SATURATE) return fail(BFP_EINVAL, "bad mode %d", mode);
-  if (w_out < 1 || w_out > z->storage_bits)
-    return fail(BFP_EWIDTH, "w_out %d outside 1..%d", w_out, z->storage_bits);
+  if (w_out < 1 || w_out > z->w)
+    return fail(BFP_EWIDTH, "w_out %d outside 1..%d (the width of z)", w_out, z->w);
   if (A->ndim != x->ndim || x->ndim != z->ndim || (y && y->ndim != z->ndim))
     return fail(BFP_ESHAPE, "dimension mismatch");
   if (y && y->n != z->n) return fail(BFP_ESHAPE, "y and z differ in size");
@@ -264,6 +280,8 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
   op.alpha_e = al->exp;
   op.beta_m = y ? be->m : 0;
   op.beta_e = y ? be->exp : 0;
+  op.abits = term_bits(am, tap_sum(taps, 27), x->w);
+  op.bbits = y ? term_bits(be->m, 1, y->w) : 0;
   if ((rc = fill_gamma(gamma, mode, &op.g))) return rc;
 
   if (A->kind == BFP_STENCIL_A) {
@@ -327,8 +345,8 @@ int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta
   int rc;
   if ((rc = check_vec(x, "x")) || (rc = check_vec(z, "z"))) return rc;
   if (y && (rc = check_vec(y, "y"))) return rc;
-  if (w_out < 1 || w_out > z->storage_bits)
-    return fail(BFP_EWIDTH, "w_out %d outside 1..%d", w_out, z->storage_bits);
+  if (w_out < 1 || w_out > z->w)
+    return fail(BFP_EWIDTH, "w_out %d outside 1..%d (the width of z)", w_out, z->w);
   if (x->ndim != z->ndim || x->n != z->n || (y && (y->ndim != z->ndim || y->n != z->n)))
     return fail(BFP_ESHAPE, "pointwise operands differ in shape");
   if ((rc = check_scalar(alpha, "alpha", 32))) return rc;
@@ -340,6 +358,8 @@ int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta
   L.op.alpha_e = alpha->exp;
   L.op.beta_m = y ? beta->m : 0;
   L.op.beta_e = y ? beta->exp : 0;
+  L.op.abits = term_bits(alpha->m, 1, x->w);
+  L.op.bbits = y ? term_bits(beta->m, 1, y->w) : 0;
   L.x = x->mant;
   L.y = y ? y->mant : nullptr;
   L.z = z->mant;
@@ -508,6 +528,7 @@ int bfp_vec_assign(bfp_vec* v, int64_t exp, void* stream) {
   PointLaunch L{};
   fill_common(&L.op, v->w, v, nullptr, v);
   L.op.alpha_m = 1;
+  L.op.abits = term_bits(1, 1, v->w);
   L.op.assign_exp = exp;
   L.op.mode = kModeAssign;
   L.x = v->mant;

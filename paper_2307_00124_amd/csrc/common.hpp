@@ -49,6 +49,7 @@ struct OpArgs {
   GammaArgs g;
   int64_t lo, hi;           // X_w_out
   int64_t assign_exp;       // kModeAssign only
+  int abits, bbits;         // |alpha S x| < 2^abits and |beta y| < 2^bbits
 };
 
 // A padded, row-pitched grid: rows = (n+2)^(ndim-1) rows of `pitch` elements.

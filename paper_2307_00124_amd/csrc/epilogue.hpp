@@ -66,11 +66,16 @@ struct Epi {
   int64_t alpha_m, beta_m, lo, hi;
   int64_t D;       // first pass: exponent gap of the two terms
   int swap;        // first pass: the y term carries the larger exponent
-  // fast path: the output exponent lies at or above both terms, so
-  // floor(hi 2^-Ls + lo 2^-Ll) = (hi + floor(lo / 2^(Ll-Ls))) >> Ls exactly,
-  // with no possible overflow (|hi|, |lo| < 2^61)
+  // Fast path, exact whenever no intermediate can overflow: with la, lb the
+  // shifts that bring the terms to the output exponent (la = ea - eo) and
+  // h / l the term with the larger / smaller shift,
+  //   both <= 0:  floor(h 2^sh + l 2^sl) = (h + (l >> (sh - sl))) >> -sh
+  //   sh >= 0:    floor(h 2^sh + l 2^sl) = (h << sh) + floor(l 2^sl)
+  // so one expression ((h << fa) + ((l << fb) >> fc)) >> fs covers both;
+  // the second case is taken only when |h| 2^sh and |l| 2^max(sl,0) stay
+  // below 2^62 (bit bounds from the host), else the generic combine runs.
   int fast;
-  int fswap, fd, fs;
+  int fswap, fa, fb, fc, fs;
   int32_t tsat;
   int32_t tmax, tmin;
   int64_t tmu;
@@ -85,19 +90,38 @@ struct Epi {
     zm = op.z_meta;
     swap = R.ea < R.eb;
     D = swap ? R.eb - R.ea : R.ea - R.eb;
-    const int64_t sa = R.sa, sb = R.eb - R.eo;
+    const int64_t la = R.sa, lb = R.eb - R.eo;
+    auto c63 = [](int64_t v) { return (int)(v > 63 ? 63 : v); };
     if (HASY) {
-      fast = sa <= 0 && sb <= 0;
-      fswap = sa < sb;                       // the term with the larger shift is "hi"
-      const int64_t s_hi = fswap ? sb : sa, s_lo = fswap ? sa : sb;
-      const int64_t dd = s_hi - s_lo, ss = -s_hi;
-      fd = (int)(dd > 63 ? 63 : dd);
-      fs = (int)(ss > 63 ? 63 : ss);
+      fswap = la < lb;
+      const int64_t sh = fswap ? lb : la, sl = fswap ? la : lb;
+      const int hb = fswap ? op.bbits : op.abits, lb_bits = fswap ? op.abits : op.bbits;
+      if (sh <= 0) {
+        fast = 1;
+        fa = 0;
+        fb = 0;
+        fc = c63(sh - sl);
+        fs = c63(-sh);
+      } else {
+        fa = (int)(sh > 62 ? 62 : sh);
+        fb = sl > 0 ? (int)sl : 0;
+        fc = sl < 0 ? c63(-sl) : 0;
+        fs = 0;
+        fast = hb + sh <= 62 && lb_bits + fb <= 62;
+      }
     } else {
-      fast = sa <= 0;
       fswap = 0;
-      fd = 0;
-      fs = (int)(-sa > 63 ? 63 : -sa);
+      fb = 0;
+      fc = 0;
+      if (la <= 0) {
+        fast = 1;
+        fa = 0;
+        fs = c63(-la);
+      } else {
+        fa = (int)(la > 62 ? 62 : la);
+        fs = 0;
+        fast = op.abits + la <= 62;
+      }
     }
     tmax = 0;
     tmin = 0;
@@ -116,11 +140,11 @@ struct Epi {
   template <int VAR>
   __device__ __forceinline__ int64_t value(int64_t g, int32_t yv) const {
     const int64_t a = VAR == kVarFastA1 ? g : mul_a(g);
-    if (!HASY) return VAR != kVarGen ? (a >> fs) : scale1(a, R.sa);
+    if (!HASY) return VAR != kVarGen ? ((a << fa) >> fs) : scale1(a, R.sa);
     const int64_t b = mul_b(yv);
     if (VAR != kVarGen) {
       const int64_t h = fswap ? b : a, l = fswap ? a : b;
-      return (h + (l >> fd)) >> fs;
+      return ((h << fa) + ((l << fb) >> fc)) >> fs;
     }
     return combine(R.cmb, a, b);
   }

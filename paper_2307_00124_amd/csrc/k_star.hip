@@ -1,218 +1,20 @@
-// Star stencils (centre + 2 ndim face taps) on one grid: the 5-point (2D)
-// and 7-point (3D) operators A' of the D = I setup, fused with the exact
-// alpha A x + beta y epilogue (the exact gemv rows of Appendix B) and the
-// qcomp / nnqcomp quantization.
-//
-// Layout: each wave owns 256 consecutive x columns (4 per lane, one 16-byte
-// load for int32 mantissas) and marches through `rows` rows (2D, in y) or
-// planes (3D, in z), keeping the previous / current / next line in
-// registers, so each input line is read from HBM once per march. The x
-// neighbours come from adjacent lanes (wave shuffles); only the two wave-edge
-// lanes load a single extra element. In 3D the y neighbours are the lines
-// of the waves above / below, read through L2.
-#include "epilogue.hpp"
+// Dispatch of the star stencil kernels on the storage type of x (the kernels
+// live in star_impl.hpp, instantiated by k_star_x8/x16/x32.hip).
+#include "kernels.hpp"
 
 namespace bfpk {
 
-// U rows per batch, software-pipelined: the loads of batch i+1 (U new x
-// lines, U y lines, the wave-edge neighbours) are issued before batch i is
-// computed and stored. Stores count in the same vector-memory counter as
-// loads, so issuing the next loads first keeps the wait for them from also
-// waiting on this batch's store acknowledgements.
-template <typename TX, typename TY, int U, bool HASY>
-__device__ __forceinline__ void star2d_fetch(const TX* X, const TY* Y, int64_t r, int64_t n,
-                                             int64_t px, int64_t py, int64_t c, int lane,
-                                             bool act, bool act_y, int32_t (&xl)[U][4],
-                                             int32_t (&yl)[U][4], int32_t (&eg)[U]) {
-#pragma unroll
-  for (int k = 0; k < U; ++k) {
-    const int64_t rr = r + 1 + k;                    // x lines r+1 .. r+U
-    ld4(X, rr * px + c, xl[k], act && rr <= n + 1);
-    if (HASY) ld4(Y, (r + k) * py + c, yl[k], act_y && r + k <= n);
-    else yl[k][0] = yl[k][1] = yl[k][2] = yl[k][3] = 0;
-    // lane 0 needs column c-1, lane 63 column c+4 (other lanes read a
-    // harmless in-range value and ignore it)
-    const int64_t re = r + k <= n ? r + k : n;
-    const int64_t ce = lane == 0 ? c - 1 : c + 4;
-    eg[k] = ld1(X, re * px + ce, (lane == 0 || lane == 63) && ce >= 0 && ce < px);
-  }
-}
-
-template <typename TX, typename TY, typename TZ, int PASS, bool HASY, bool WIDE, int U>
-__global__ __launch_bounds__(kBlock) void k_star2d(const StarLaunch L) {
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t n = L.n, px = L.px, py = L.py, pz = L.pz;
-  const int64_t c = (int64_t)blockIdx.x * 256 + lane * 4;
-  const bool act = c < px, act_y = c < py, act_z = c < pz;
-  const int64_t r0 = 1 + ((int64_t)blockIdx.y * 4 + wv) * L.rows;
-  int64_t r1 = r0 + L.rows;
-  if (r1 > n + 1) r1 = n + 1;
-  const TX* X = static_cast<const TX*>(L.x);
-  const TY* Y = static_cast<const TY*>(L.y);
-  TZ* Z = static_cast<TZ*>(L.z);
-  const int32_t t0 = L.taps[0], txm = L.taps[1], txp = L.taps[2], tym = L.taps[3],
-                typ = L.taps[4];
-  Epi<PASS, HASY> E;
-  E.init(L.op);
-  bool colok[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) colok[q] = c + q >= 1 && c + q <= n;
-  if (r0 < r1) with_fast(E, [&](auto fast_tag) {
-    constexpr int VAR = decltype(fast_tag)::value;
-    int32_t win[U + 2][4];                 // lines r-1 .. r+U of the current batch
-    int32_t yv[U][4], eg[U];
-    int32_t nx[U][4], ny[U][4], ne[U];     // the next batch in flight
-    ld4(X, (r0 - 1) * px + c, win[0], act);
-    ld4(X, r0 * px + c, win[1], act);
-    star2d_fetch<TX, TY, U, HASY>(X, Y, r0, n, px, py, c, lane, act, act_y,
-                                  *reinterpret_cast<int32_t(*)[U][4]>(&win[2]), yv, eg);
-    for (int64_t r = r0; r < r1; r += U) {
-      star2d_fetch<TX, TY, U, HASY>(X, Y, r + U, n, px, py, c, lane, act, act_y, nx, ny, ne);
-#pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const int32_t* up = win[k];
-        const int32_t* cur = win[k + 1];
-        const int32_t* dn = win[k + 2];
-        int32_t left = __shfl_up(cur[3], 1, 64);
-        int32_t right = __shfl_down(cur[0], 1, 64);
-        if (lane == 0) left = eg[k];
-        if (lane == 63) right = eg[k];
-        const bool row_ok = r + k < r1;
-        int64_t out[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int32_t xl = q ? cur[q - 1] : left;
-          const int32_t xr = q < 3 ? cur[q + 1] : right;
-          int64_t g;
-          if (WIDE)
-            g = (int64_t)t0 * cur[q] + (int64_t)txm * xl + (int64_t)txp * xr +
-                (int64_t)tym * up[q] + (int64_t)typ * dn[q];
-          else
-            g = (int64_t)(t0 * cur[q] + txm * xl + txp * xr + tym * up[q] + typ * dn[q]);
-          out[q] = E.template put<VAR>(g, yv[k][q], row_ok && colok[q]);
-        }
-        if (PASS != kQ1 && act_z && row_ok) st4(Z, (r + k) * pz + c, out);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        win[0][q] = win[U][q];
-        win[1][q] = win[U + 1][q];
-      }
-#pragma unroll
-      for (int k = 0; k < U; ++k) {
-        eg[k] = ne[k];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          win[k + 2][q] = nx[k][q];
-          yv[k][q] = ny[k][q];
-        }
-      }
-    }
-  });
-  E.finish();
-}
-
-template <typename TX, typename TY, typename TZ, int PASS, bool HASY>
-__global__ __launch_bounds__(kBlock) void k_star3d(const StarLaunch L) {
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t n = L.n, px = L.px, py = L.py, pz = L.pz;
-  const int64_t side = n + 2;
-  const int64_t c = (int64_t)blockIdx.x * 256 + lane * 4;
-  const bool act = c < px, act_y = c < py, act_z = c < pz;
-  const int64_t yr = 1 + (int64_t)blockIdx.y * 4 + wv;
-  const int64_t z0 = 1 + (int64_t)blockIdx.z * L.rows;
-  int64_t z1 = z0 + L.rows;
-  if (z1 > n + 1) z1 = n + 1;
-  const TX* X = static_cast<const TX*>(L.x);
-  const TY* Y = static_cast<const TY*>(L.y);
-  TZ* Z = static_cast<TZ*>(L.z);
-  const int32_t t0 = L.taps[0], txm = L.taps[1], txp = L.taps[2], tym = L.taps[3],
-                typ = L.taps[4], tzm = L.taps[5], tzp = L.taps[6];
-  Epi<PASS, HASY> E;
-  E.init(L.op);
-  if (yr <= n && z0 < z1) with_fast(E, [&](auto fast_tag) {
-    constexpr int VAR = decltype(fast_tag)::value;
-    int32_t zm[4], cur[4], zp[4], ym[4], yp[4], yv[4] = {0, 0, 0, 0};
-    ld4(X, ((z0 - 1) * side + yr) * px + c, zm, act);
-    ld4(X, (z0 * side + yr) * px + c, cur, act);
-    for (int64_t z = z0; z < z1; ++z) {
-      const int64_t row = z * side + yr;
-      ld4(X, (row + side) * px + c, zp, act);
-      ld4(X, (row - 1) * px + c, ym, act);
-      ld4(X, (row + 1) * px + c, yp, act);
-      if (HASY) ld4(Y, row * py + c, yv, act_y);
-      int32_t left = __shfl_up(cur[3], 1, 64);
-      int32_t right = __shfl_down(cur[0], 1, 64);
-      const int64_t ce = lane == 0 ? c - 1 : c + 4;
-      const int32_t edge = ld1(X, row * px + ce, (lane == 0 || lane == 63) && ce >= 0 && ce < px);
-      if (lane == 0) left = edge;
-      if (lane == 63) right = edge;
-      int64_t out[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int32_t xl = k ? cur[k - 1] : left;
-        const int32_t xr = k < 3 ? cur[k + 1] : right;
-        const int64_t g = (int64_t)t0 * cur[k] + (int64_t)txm * xl + (int64_t)txp * xr +
-                          (int64_t)tym * ym[k] + (int64_t)typ * yp[k] +
-                          (int64_t)tzm * zm[k] + (int64_t)tzp * zp[k];
-        const int64_t col = c + k;
-        out[k] = E.template put<VAR>(g, yv[k], col >= 1 && col <= n);
-      }
-      if (PASS != kQ1 && act_z) st4(Z, row * pz + c, out);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) { zm[k] = cur[k]; cur[k] = zp[k]; }
-    }
-  });
-  E.finish();
-}
-
-// ----------------------------------------------------------- launchers --
-
-template <typename TX, typename TY, typename TZ, int PASS, bool HASY>
-static hipError_t star_go(const StarLaunch& L, hipStream_t s) {
-  const int64_t n = L.n;
-  const int rows = L.rows > 0 ? L.rows : 1;
-  if (L.ndim == 2) {
-    dim3 grid((unsigned)((n + 1 + 255) / 256), (unsigned)((n + 4 * rows - 1) / (4 * rows)));
-    if (rows >= 4 && rows % 4 == 0) {
-      if (L.wide)
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, true, 4>), grid, dim3(kBlock), 0, s, L);
-      else
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, false, 4>), grid, dim3(kBlock), 0, s, L);
-    } else {
-      if (L.wide)
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, true, 1>), grid, dim3(kBlock), 0, s, L);
-      else
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, false, 1>), grid, dim3(kBlock), 0, s, L);
-    }
-  } else {
-    dim3 grid((unsigned)((n + 1 + 255) / 256), (unsigned)((n + 3) / 4),
-              (unsigned)((n + rows - 1) / rows));
-    hipLaunchKernelGGL((k_star3d<TX, TY, TZ, PASS, HASY>), grid, dim3(kBlock), 0, s, L);
-  }
-  return hipGetLastError();
-}
+hipError_t launch_star_x8(const StarLaunch& L, hipStream_t s);
+hipError_t launch_star_x16(const StarLaunch& L, hipStream_t s);
+hipError_t launch_star_x32(const StarLaunch& L, hipStream_t s);
 
 hipError_t launch_star(const StarLaunch& L, hipStream_t s) {
-  const bool q1 = L.op.mode == kModeQ1;
-  return with_type(L.xbits, [&](auto tx) {
-    using TX = decltype(tx);
-    if (!L.op.has_y) {
-      if (q1) return star_go<TX, int32_t, int32_t, kQ1, false>(L, s);
-      return with_type(L.zbits, [&](auto tz) {
-        return star_go<TX, int32_t, decltype(tz), kOut, false>(L, s);
-      });
-    }
-    return with_type(L.ybits, [&](auto ty) {
-      using TY = decltype(ty);
-      if (q1) return star_go<TX, TY, int32_t, kQ1, true>(L, s);
-      return with_type(L.zbits, [&](auto tz) {
-        return star_go<TX, TY, decltype(tz), kOut, true>(L, s);
-      });
-    });
-  });
+  switch (L.xbits) {
+    case 8: return launch_star_x8(L, s);
+    case 16: return launch_star_x16(L, s);
+    case 32: return launch_star_x32(L, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace bfpk

@@ -162,6 +162,39 @@ def test_huge_exponent_gaps(ndim):
             assert_block_equal(z, quantize_ref(op, mode, 24, gr), f"gap {gap} mode {mode}")
 
 
+@pytest.mark.parametrize("ndim,n", [(2, 300), (3, 19)])
+@pytest.mark.parametrize("alpha,beta", [((1, 0), (-1, 0)), ((3, -1), (-5, 2))])
+def test_output_exponent_sweep(ndim, n, alpha, beta):
+    """Nearly cancelling alpha A x + beta y quantized at output exponents from
+    10 bits above to 45 bits below the exact terms' exponents: the right-shift
+    and left-shift branches of the fast epilogue, the edge of its overflow
+    bound and the generic combine beyond it."""
+    g = np.random.default_rng(100 * ndim + alpha[0])
+    Ad, Ao = fd_A(ndim)
+    x = rand_block(g, ndim, n, 24, 3)
+    al, be = Scalar(alpha[0], alpha[1], 4), Scalar(beta[0], beta[1], 4)
+    # y ~ -(alpha / beta) A x at the exponent of alpha A x, plus small noise
+    gx = Ao.apply(x.m)
+    ey = Ao.e + x.e + al.e - be.e
+    inner = np.zeros(gx.shape, dtype=bool)
+    inner[(slice(1, -1),) * ndim] = True
+    noise = g.integers(-(1 << 6), 1 << 6, size=gx.shape)
+    ym = np.where(inner, -(gx * al.m) // be.m + noise, 0)
+    y = BFP(ey, as_block(np.asarray(ym, dtype=object)), 32)
+    assert y.fits()
+    xd, yd = upload(x), upload(y)
+    ea = Ao.e + x.e + al.e
+    for shift in range(-10, 46, 3):
+        # e_out = nu(gamma) - w_out = ge + 2 - 24 puts the output `shift` bits below ea
+        ge = ea - shift + 22
+        z = P.Vec(ndim, n, 24, 32)
+        P.bfp_stencil_apply(Ad, xd, P.scalar(al.m, al.e), P.scalar(be.m, be.e), yd, 24,
+                            P.BFP_SATURATE, P.gamma_explicit(1, ge), z)
+        op = blas.gemv(Ao, x, y, al, be)
+        ref = blas.nnqcomp(op, 24, Fraction(2) ** ge)[0]
+        assert_block_equal(z, ref, f"output {shift} bits below the terms")
+
+
 # ------------------------------------------------------------ transfers --
 
 @pytest.mark.parametrize("ndim,nc", [(2, 1), (2, 3), (2, 15), (2, 150), (3, 1), (3, 3), (3, 9)])
@@ -214,9 +247,10 @@ def test_axpy_and_sub(ndim, n, mode):
         z2 = P.Vec(ndim, n, wz, bz)
         P.bfp_sub(xd, yd, wz, mode, gd, z2)
         assert_block_equal(z2, quantize_ref(blas.sub(x, y), mode, wz, gr), "sub")
-        # in place: z aliases y
-        P.bfp_sub(xd, yd, min(wz, by), mode, gd, yd)
-        assert_block_equal(yd, quantize_ref(blas.sub(x, y), mode, min(wz, by), gr), "sub in place")
+        # in place: z aliases y (the output width may not exceed y's own)
+        P.bfp_sub(xd, yd, min(wz, y.w), mode, gd, yd)
+        assert_block_equal(yd, quantize_ref(blas.sub(x, y), mode, min(wz, y.w), gr),
+                           "sub in place")
 
 
 @pytest.mark.parametrize("ndim,n", [(2, 5), (2, 200), (3, 6)])

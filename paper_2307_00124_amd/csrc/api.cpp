@@ -58,6 +58,36 @@ static int record(const L& launch, int exec_mode) {
   return BFP_OK;
 }
 
+int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas) {
+  metas.clear();
+  auto slot_of = [&](const int64_t* p) -> int16_t {
+    if (!p) return -1;
+    for (size_t i = 0; i < metas.size(); ++i)
+      if (metas[i] == p) return (int16_t)i;
+    metas.push_back(const_cast<int64_t*>(p));
+    return (int16_t)(metas.size() - 1);
+  };
+  for (ExecOp& e : ops) {
+    const OpArgs* a = e.kind == kExStar       ? &e.u.star.op
+                      : e.kind == kExTransfer ? &e.u.tr.op
+                      : e.kind == kExPoint    ? &e.u.pt.op
+                                              : nullptr;
+    for (int i = 0; i < 5; ++i) e.slot[i] = -1;
+    if (a) {
+      e.slot[0] = slot_of(a->x_meta);
+      e.slot[1] = a->has_y ? slot_of(a->y_meta) : -1;
+      e.slot[2] = slot_of(a->z_meta);
+      e.slot[3] = slot_of(a->g.a);
+      e.slot[4] = slot_of(a->g.b);
+    } else {
+      e.slot[2] = slot_of(e.u.zero.meta);
+    }
+    if (metas.size() > (size_t)kExecMaxMeta)
+      return fail(BFP_EINVAL, "a recorded program touches more than %d blocks", kExecMaxMeta);
+  }
+  return BFP_OK;
+}
+
 static int star_rows(int ndim, int64_t n) {
   if (ndim == 2) {
     if (g_star2d_rows_large > 0) return n < g_star2d_small_n ? 1 : g_star2d_rows_large;

@@ -36,5 +36,8 @@ void record_into(std::vector<ExecOp>* sink);
 bool recording();
 // grids of at most this many points run inside recorded programs (0: never)
 int exec_max_points();
+// Give every op of a recorded program the slots of its metadata blocks in
+// the program's table of distinct blocks (filled into `metas`).
+int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas);
 
 }  // namespace bfpk

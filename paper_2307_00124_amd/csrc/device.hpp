@@ -104,22 +104,34 @@ __device__ __forceinline__ int msb_exact2(int64_t hi, int64_t lo, int64_t D) {
 
 // nu(gamma) = floor(log2 gamma) + 2 for the device-evaluated estimate, or
 // sets *zero when gamma = 0.
-__device__ __forceinline__ int64_t norm_mag(const int64_t* m) {
-  int64_t mx = m[kMetaMax], mn = m[kMetaMin];
+// Metadata reads of an op go through an accessor: ma(k, f) is field f of
+// operand k (kOpX, kOpY, kOpZ, or the estimate's blocks kOpGa, kOpGb).
+enum { kOpX = 0, kOpY = 1, kOpZ = 2, kOpGa = 3, kOpGb = 4 };
+
+// the operands' metadata in global memory, through the op's pointers
+struct PtrMeta {
+  const int64_t* p[5];
+  __device__ __forceinline__ int64_t operator()(int k, int f) const { return p[k][f]; }
+};
+
+template <class MA>
+__device__ __forceinline__ int64_t norm_mag(const MA& ma, int k) {
+  const int64_t mx = ma(k, kMetaMax), mn = ma(k, kMetaMin);
   return mx > -mn ? mx : -mn;
 }
 
-__device__ __forceinline__ int64_t gamma_nu(const GammaArgs& g, bool* zero) {
+template <class MA>
+__device__ __forceinline__ int64_t gamma_nu(const GammaArgs& g, const MA& ma, bool* zero) {
   *zero = false;
   if (g.rule == kGammaNorm) {
-    int64_t M = norm_mag(g.a);
+    int64_t M = norm_mag(ma, kOpGa);
     if (M == 0) { *zero = true; return 0; }
     uint64_t prod = (uint64_t)M * (uint64_t)g.cm;
-    return (int64_t)bitlen64(prod) + 1 + g.ce + g.a[kMetaExp];
+    return (int64_t)bitlen64(prod) + 1 + g.ce + ma(kOpGa, kMetaExp);
   }
   if (g.rule == kGammaSum) {
-    int64_t Ma = norm_mag(g.a), Mb = norm_mag(g.b);
-    int64_t ea = g.a[kMetaExp], eb = g.b[kMetaExp];
+    int64_t Ma = norm_mag(ma, kOpGa), Mb = norm_mag(ma, kOpGb);
+    int64_t ea = ma(kOpGa, kMetaExp), eb = ma(kOpGb, kMetaExp);
     if (Ma == 0 && Mb == 0) { *zero = true; return 0; }
     if (Ma == 0) return (int64_t)bitlen64((uint64_t)Mb) + 1 + eb;
     if (Mb == 0) return (int64_t)bitlen64((uint64_t)Ma) + 1 + ea;
@@ -135,6 +147,31 @@ __device__ __forceinline__ int64_t gamma_nu(const GammaArgs& g, bool* zero) {
 }
 
 // ------------------------------------------------ metadata reductions --
+
+// Wave-wide reductions of 32-bit values with DPP (no LDS round trips): a
+// scan within each row of 16 lanes (row_shr 1, 2, 4, 8), then the row
+// totals are carried forward (row_bcast 15 into rows 1 and 3, row_bcast 31
+// into rows 2 and 3), so lane 63 ends with the reduction of all 64 lanes.
+// Lanes whose DPP source is out of range read `id`, the identity.
+template <typename F>
+__device__ __forceinline__ int32_t wave_reduce32(int32_t v, int32_t id, F op) {
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int32_t wave_max32(int32_t v) {
+  return wave_reduce32(v, INT32_MIN, [](int32_t a, int32_t b) { return a > b ? a : b; });
+}
+__device__ __forceinline__ int32_t wave_min32(int32_t v) {
+  return wave_reduce32(v, INT32_MAX, [](int32_t a, int32_t b) { return a < b ? a : b; });
+}
+__device__ __forceinline__ int32_t wave_sum32(int32_t v) {
+  return wave_reduce32(v, 0, [](int32_t a, int32_t b) { return a + b; });
+}
 
 __device__ __forceinline__ int64_t wave_max(int64_t v) {
   for (int o = 32; o > 0; o >>= 1) { int64_t t = __shfl_xor(v, o, 64); v = t > v ? t : v; }
@@ -299,20 +336,21 @@ struct Resolved {
   int64_t sa;    // single-term shift when there is no y
 };
 
-__device__ __forceinline__ Resolved resolve(const OpArgs& p) {
+template <class MA>
+__device__ __forceinline__ Resolved resolve(const OpArgs& p, const MA& ma) {
   Resolved r;
-  r.ea = p.alpha_e + p.e_A + p.x_meta[kMetaExp];
-  r.eb = p.has_y ? p.beta_e + p.y_meta[kMetaExp] : r.ea;
+  r.ea = p.alpha_e + p.e_A + ma(kOpX, kMetaExp);
+  r.eb = p.has_y ? p.beta_e + ma(kOpY, kMetaExp) : r.ea;
   r.ez = r.ea < r.eb ? r.ea : r.eb;
   if (p.mode == kModeSat) {
     bool zero;
-    int64_t nu = gamma_nu(p.g, &zero);
+    int64_t nu = gamma_nu(p.g, ma, &zero);
     r.eo = zero ? r.ez + 1 - p.w_out : nu - p.w_out;
   } else if (p.mode == kModeQ2) {
-    r.eo = r.ez + p.z_meta[kMetaMu] - p.w_out;
+    r.eo = r.ez + ma(kOpZ, kMetaMu) - p.w_out;
   } else if (p.mode == kModeNormMeta) {
     // mu* of a stored block from its max / min (msb is monotone in |v|)
-    int64_t a = msb64(p.x_meta[kMetaMax]), b = msb64(p.x_meta[kMetaMin]);
+    int64_t a = msb64(ma(kOpX, kMetaMax)), b = msb64(ma(kOpX, kMetaMin));
     r.eo = r.ez + (a > b ? a : b) - p.w_out;
   } else if (p.mode == kModeAssign) {
     r.eo = p.assign_exp;
@@ -322,6 +360,10 @@ __device__ __forceinline__ Resolved resolve(const OpArgs& p) {
   r.sa = p.mode == kModeAssign ? 0 : r.ea - r.eo;
   r.cmb = make_combine(r.ea - r.eo, r.eb - r.eo);
   return r;
+}
+
+__device__ __forceinline__ PtrMeta ptr_meta(const OpArgs& p) {
+  return PtrMeta{{p.x_meta, p.y_meta, p.z_meta, p.g.a, p.g.b}};
 }
 
 __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi, int64_t& sat) {

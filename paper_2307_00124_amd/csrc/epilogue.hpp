@@ -81,8 +81,11 @@ struct Epi {
   int64_t tmu;
   int64_t* zm;
 
-  __device__ __forceinline__ void init(const OpArgs& op) {
-    R = resolve(op);
+  __device__ __forceinline__ void init(const OpArgs& op) { init(op, ptr_meta(op)); }
+
+  template <class MA>
+  __device__ __forceinline__ void init(const OpArgs& op, const MA& ma) {
+    R = resolve(op, ma);
     alpha_m = op.alpha_m;
     beta_m = op.beta_m;
     lo = op.lo;

@@ -104,6 +104,9 @@ struct ZeroOp {
 struct ExecOp {
   int kind;
   int mode;   // kModeSat, kModeNormMeta, kModeAssign or kExModeQ
+  // metadata slots (x, y, z, gamma a, gamma b; -1 = none) in the program's
+  // table of distinct metadata blocks, which the executor mirrors in LDS
+  int16_t slot[5];
   union {
     StarLaunch star;
     TransferLaunch tr;
@@ -114,8 +117,14 @@ struct ExecOp {
 
 // Run ops[0..count) in order inside one workgroup of kExecThreads threads;
 // every op works on grids of one dimension ndim with n_out < kExecMaxN.
+// metas[0..nmeta) are the metadata blocks the ops name by slot: the
+// executor works on an LDS copy of their first kExMetaF fields and writes
+// it back at the end.
 constexpr int kExecThreads = 1024;
 constexpr int kExecMaxN = 1024;
-hipError_t launch_exec(const ExecOp* ops_dev, int count, int ndim, hipStream_t s);
+constexpr int kExecMaxMeta = 64;
+constexpr int kExMetaF = 8;
+hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_dev, int nmeta,
+                       int ndim, hipStream_t s);
 
 }  // namespace bfpk

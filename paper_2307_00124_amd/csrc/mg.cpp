@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -43,6 +44,8 @@ struct Level {
 struct Program {
   ExecOp* ops;
   int count;
+  int64_t** metas;   // table of the metadata blocks the ops name by slot
+  int nmeta;
   double bytes;
 };
 
@@ -170,7 +173,8 @@ int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, int 
 }
 
 int run_program(mg_hierarchy* h, const Program& pg, hipStream_t s) {
-  int rc = hip_check(launch_exec(pg.ops, pg.count, h->prm.ndim, s), "coarse-level program");
+  int rc = hip_check(launch_exec(pg.ops, pg.count, pg.metas, pg.nmeta, h->prm.ndim, s),
+                     "coarse-level program");
   if (rc) return rc;
   h->bytes += pg.bytes;
   h->launches += 1;
@@ -358,6 +362,9 @@ size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops) {
       off = align256(off + kMetaSlots * sizeof(int64_t));
     }
   }
+  h->progV.metas = base ? (int64_t**)(base + off) : nullptr;
+  h->progF.metas = base ? (int64_t**)(base + off) + kExecMaxMeta : nullptr;
+  off = align256(off + 2 * kExecMaxMeta * sizeof(int64_t*));
   h->progV.ops = base ? (ExecOp*)(base + off) : nullptr;
   off = align256(off + nops * sizeof(ExecOp));
   return off;
@@ -519,19 +526,32 @@ int mg_hierarchy_create(const mg_params* prm, void* arena_dev, size_t bytes, voi
     }
   }
   std::vector<ExecOp> V, F;
-  if ((rc = record_programs(h, &V, &F, &h->progV.bytes, &h->progF.bytes))) { delete h; return rc; }
+  std::vector<int64_t*> mV, mF;
+  if ((rc = record_programs(h, &V, &F, &h->progV.bytes, &h->progF.bytes)) ||
+      (rc = exec_assign_slots(V, mV)) || (rc = exec_assign_slots(F, mF))) {
+    delete h;
+    return rc;
+  }
   if (V.size() + F.size() != nops) {
     delete h;
     return fail(BFP_EINVAL, "recorded programs changed size (%zu vs %zu ops)", V.size() + F.size(), nops);
   }
   h->progV.count = (int)V.size();
+  h->progV.nmeta = (int)mV.size();
   h->progF.ops = h->progV.ops + V.size();
   h->progF.count = (int)F.size();
+  h->progF.nmeta = (int)mF.size();
   if (nops) {
     std::vector<ExecOp> all(V);
     all.insert(all.end(), F.begin(), F.end());
+    std::vector<int64_t*> tables(2 * kExecMaxMeta, nullptr);
+    std::copy(mV.begin(), mV.end(), tables.begin());
+    std::copy(mF.begin(), mF.end(), tables.begin() + kExecMaxMeta);
     rc = hip_check(hipMemcpyAsync(h->progV.ops, all.data(), nops * sizeof(ExecOp),
                                   hipMemcpyHostToDevice, s), "program upload");
+    if (!rc)
+      rc = hip_check(hipMemcpyAsync(h->progV.metas, tables.data(), tables.size() * sizeof(int64_t*),
+                                    hipMemcpyHostToDevice, s), "program upload");
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "program upload");
     if (rc) { delete h; return rc; }
   }

@@ -153,11 +153,11 @@ def _ratio(x, L, ndim):
     return fp64.l2_error(x.to_f64(), us, L) / fp64.l2_error(uh, us, L)
 
 
-def test_op_count_structure_matches_table3():
+def test_op_count_structure_matches_table2():
     """P8: one IR-V(1,0) iteration quantizes 6 results and an FMG level adds
     one prolongation: 6N + 1 calls on the finest level, the parenthesized
-    totals of Table 3."""
-    g = json.load(open(os.path.join(GOLDEN, "table3_call_totals.json")))
+    totals of Table 2."""
+    g = json.load(open(os.path.join(GOLDEN, "table2_call_totals.json")))
     pairs = {(e["N"], e["total"]) for e in g["poisson"] + g["biharmonic"]}
     for N, total in sorted(pairs):
         H2 = _hier(3, 2, mg.widths_fixed(3, 24))

@@ -312,6 +312,34 @@ int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out);
  * the number of kernel launches (host-side counters).                     */
 int mg_counters(const mg_hierarchy* h, double* bytes, int64_t* launches);
 
+/* ---------------------------------------------------------- batches ---
+ * Many independent problems solved together (the batched workload): each
+ * problem has its own hierarchy inside one caller-provided arena, and
+ * mg_solve_batch runs, for every problem, the FP64 -> BFP conversion of its
+ * right-hand side on every level followed by the whole FMG of mg_fmg, in ONE
+ * launch (one workgroup per problem, larger problems first). Results are
+ * bit-identical to solving each problem alone with mg_set_rhs + mg_fmg.
+ * prms[i]: the parameters of problem i (all with the same ndim, 2^L - 1 <
+ * 1024 points per dimension); problems with bitwise-identical parameters
+ * share one recorded program. Creation synchronizes `stream`.             */
+typedef struct mg_batch mg_batch;
+
+size_t mg_batch_bytes(const mg_params* prms, int nprob);      /* 0 on error */
+int mg_batch_create(const mg_params* prms, int nprob, void* arena_dev, size_t bytes,
+                    void* stream, mg_batch** out);
+int mg_batch_destroy(mg_batch* b);
+
+/* rhs_table_dev: device array of nprob * MG_MAX_LEVELS FP64 pointers; entry
+ * [i * MG_MAX_LEVELS + j - 1] is problem i's f_j on its padded level-j grid
+ * ((2^j + 1)^ndim values; ring ignored), as for mg_set_rhs.               */
+int mg_solve_batch(mg_batch* b, const double* const* rhs_table_dev, void* stream);
+
+/* Views of problem `prob`'s blocks (which as for mg_get_vec).              */
+int mg_batch_get_vec(mg_batch* b, int prob, int level, int which, bfp_vec* out);
+
+/* Algorithmic bytes of one mg_solve_batch and the launches issued so far.  */
+int mg_batch_counters(const mg_batch* b, double* bytes, int64_t* launches);
+
 /* Launch-shape tuning (process-wide; results do not depend on it):
  * "star2d_rows" / "star3d_rows" = rows or planes one wave of the star
  * stencil kernels marches on large grids, "star2d_small_n" /

@@ -340,6 +340,53 @@ class Hierarchy:
         return b.value, n.value
 
 
+class Batch:
+    """Independent problems solved together (mg_batch_* calls): one arena,
+    one launch per batched solve."""
+
+    def __init__(self, params: list, device="cuda", stream=None):
+        self.params = list(params)
+        arr = (abi.mg_params * len(self.params))(*self.params)
+        self._arr = arr
+        nbytes = lib.mg_batch_bytes(arr, len(self.params))
+        if nbytes == 0:
+            raise BFPError(abi.BFP_EINVAL, "mg_batch_bytes")
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        self.arena = self.arena[off:off + nbytes]
+        b = C.c_void_p()
+        check(lib.mg_batch_create(arr, len(self.params), _ptr(self.arena), nbytes,
+                                  _stream(stream), C.byref(b)), "mg_batch_create")
+        self.b = b
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and b.value:
+            lib.mg_batch_destroy(b)
+            self.b = None
+
+    def solve(self, rhs_table: torch.Tensor, stream=None) -> None:
+        """rhs_table: int64 device tensor of len(params) * MG_MAX_LEVELS FP64
+        device pointers (row i, column j - 1: problem i's f on level j)."""
+        if rhs_table.dtype != torch.int64 or not rhs_table.is_cuda:
+            raise ValueError("rhs_table must be an int64 device tensor of pointers")
+        if rhs_table.numel() < len(self.params) * abi.MG_MAX_LEVELS:
+            raise ValueError("rhs_table is too short")
+        check(lib.mg_solve_batch(self.b, _ptr(rhs_table), _stream(stream)), "mg_solve_batch")
+
+    def get_vec(self, prob: int, level: int, which: int = 0) -> Vec:
+        v = abi.bfp_vec()
+        check(lib.mg_batch_get_vec(self.b, prob, level, which, C.byref(v)), "mg_batch_get_vec")
+        return Vec.view(v, self)
+
+    def counters(self) -> tuple[float, int]:
+        b = C.c_double()
+        n = C.c_int64()
+        check(lib.mg_batch_counters(self.b, C.byref(b), C.byref(n)), "mg_batch_counters")
+        return b.value, n.value
+
+
 def mg_params_init(ndim: int, L: int, w: int, progressive: bool = True, nu1: int = 1,
                    nu2: int = 0, N: int = 2, policy: int = MG_POLICY_NN_IR_FIRST_Q,
                    eta_percent: int = 23, min_storage_bits: int = 0) -> abi.mg_params:
@@ -362,4 +409,15 @@ def make_params(ndim: int, L: int, w_check: dict, w_work: dict, w_inner: dict,
         p.w_work[j] = w_work[j]
         p.w_inner[j] = w_inner[j]
     p.c1, p.c2, p.c1_gamma = c1, c2, c1_gamma
+    return p
+
+
+def batch_params(ndim: int, L: int, w_inner: int = 16, nu1: int = 1, nu2: int = 0, N: int = 2,
+                 policy: int = MG_POLICY_NN_IR_FIRST_Q, eta_percent: int = 23) -> abi.mg_params:
+    """Parameters of the batched workload: A and b at 32 bits, working width
+    min(32, 2j + 8), inner width min(working, w_inner) on every level."""
+    p = mg_params_init(ndim, L, w_inner, True, nu1, nu2, N, policy, eta_percent)
+    for j in range(1, L + 1):
+        p.w_check[j] = 32
+        p.w_inner[j] = min(p.w_work[j], w_inner)
     return p

@@ -90,6 +90,12 @@ SIGNATURES = {
     "mg_vcycle": (I, [VP, I, P(bfp_vec), P(bfp_vec), VP]),
     "mg_get_vec": (I, [VP, I, I, P(bfp_vec)]),
     "mg_counters": (I, [VP, P(C.c_double), P(I64)]),
+    "mg_batch_bytes": (C.c_size_t, [P(mg_params), I]),
+    "mg_batch_create": (I, [P(mg_params), I, VP, C.c_size_t, VP, P(VP)]),
+    "mg_batch_destroy": (I, [VP]),
+    "mg_solve_batch": (I, [VP, VP, VP]),
+    "mg_batch_get_vec": (I, [VP, I, I, I, P(bfp_vec)]),
+    "mg_batch_counters": (I, [VP, P(C.c_double), P(I64)]),
     "bfp_tuning_set": (I, [C.c_char_p, I]),
     "bfp_last_error": (C.c_char_p, []),
 }

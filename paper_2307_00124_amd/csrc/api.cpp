@@ -79,6 +79,8 @@ int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas) {
       e.slot[2] = slot_of(a->z_meta);
       e.slot[3] = slot_of(a->g.a);
       e.slot[4] = slot_of(a->g.b);
+    } else if (e.kind == kExConv) {
+      e.slot[2] = slot_of(e.u.conv.meta);
     } else {
       e.slot[2] = slot_of(e.u.zero.meta);
     }

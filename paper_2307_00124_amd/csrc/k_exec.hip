@@ -1,11 +1,13 @@
-// Coarse-level executor: one workgroup of kExecThreads threads runs a
-// recorded list of BFP operations (star stencils, grid transfers, pointwise
-// ops, zero fills) one after the other, with a workgroup barrier between
+// Coarse-level executor: one workgroup runs a recorded list of BFP
+// operations (star stencils, grid transfers, pointwise ops, zero fills,
+// FP64 conversions) one after the other, with a workgroup barrier between
 // them. Each operation computes exactly what its stand-alone kernel computes
 // — the same exact row sums and the same epilogue (the generic exact
 // combine) — and publishes its metadata from a workgroup reduction, so a
 // whole coarse V-cycle, or the coarse levels of FMG, cost one launch instead
-// of one or two launches per operation.
+// of one or two launches per operation. The batched form runs one such
+// workgroup per independent problem: a whole FMG solve per workgroup, every
+// problem of a batch in one launch.
 //
 // Storage types are read at run time: loads fetch the aligned 32-bit word
 // holding an element and extract it, which keeps every load of a batch
@@ -16,13 +18,15 @@
 // written back at the end) and prefetches each recorded op into an LDS
 // double buffer while the previous one runs: per op, the only global
 // round trips left are the data loads and the store acknowledgements.
+//
+// Programs of batched problems are relocatable: their data and metadata
+// pointers are offsets that the executor adds to the problem's arena base
+// (base 0 for the absolute programs of a single hierarchy).
 #include "epilogue.hpp"
 
 namespace bfpk {
 
 namespace {
-
-constexpr int kExWaves = kExecThreads / 64;
 
 // Pointers read from the recorded ops are generic; the data all lives in
 // global memory, and saying so keeps loads and stores off the flat path
@@ -35,8 +39,13 @@ struct Src {
   int bits;
 };
 
-__device__ __forceinline__ Src src_of(const void* p, int bits) {
-  return Src{(const BFP_GLOBAL char*)p, bits == 32 ? 2 : (bits == 16 ? 1 : 0), bits};
+// relocation of a recorded pointer by the running problem's base
+__device__ __forceinline__ void* rel(const void* p, uintptr_t base) {
+  return (void*)((uintptr_t)p + base);
+}
+
+__device__ __forceinline__ Src src_of(const void* p, int bits, uintptr_t base) {
+  return Src{(const BFP_GLOBAL char*)rel(p, base), bits == 32 ? 2 : (bits == 16 ? 1 : 0), bits};
 }
 
 // element i, sign-extended from its storage width
@@ -75,9 +84,17 @@ __device__ __forceinline__ LdsMeta lds_meta(MetaRow* lm, const int16_t* slot) {
 
 // Workgroup reductions: per-wave partials (DPP) in LDS, then wave 0
 // reduces them and lane 0 publishes the result in the output's LDS row.
-template <int PASS, bool HASY>
+template <int NT>
+struct Red {
+  static constexpr int kWaves = NT / 64;
+  int32_t v[3][kWaves];
+};
+
+template <int NT, int PASS, bool HASY>
 __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm) {
-  __shared__ int32_t red[3][kExWaves];
+  constexpr int kExWaves = NT / 64;
+  __shared__ Red<NT> R;
+  auto& red = R.v;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (PASS == kQ1) {
     const int32_t m = wave_max32((int32_t)E.tmu);
@@ -116,25 +133,26 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm)
 // Points are enumerated on a 2^lg >= n padded index space; a padding slot
 // becomes the interior point (1, 1, 1), which keeps every address in bounds,
 // and is neither stored nor counted.
-template <int ND, int PASS, bool HASY, int U, typename Gather>
-__device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, int n,
-                                        const void* yp, int ybits, int64_t py, void* zp,
+template <int NT, int ND, int PASS, bool HASY, int U, typename Gather>
+__device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uintptr_t base,
+                                        int n, const void* yp, int ybits, int64_t py, void* zp0,
                                         int zbits, int64_t pz, Gather&& gather) {
   Epi<PASS, HASY> E;
   E.init(op, ma);
-  const Src ys = src_of(yp, ybits);
+  const Src ys = src_of(yp, ybits, base);
+  void* zp = rel(zp0, base);
   int lg = 0;
   while ((1 << lg) < n) ++lg;
   const int M = (1 << lg) - 1;
   const int tot = ND == 3 ? 1 << (3 * lg) : 1 << (2 * lg);
   const int64_t side = n + 2;
-  for (int i0 = threadIdx.x; i0 < tot; i0 += U * kExecThreads) {
+  for (int i0 = threadIdx.x; i0 < tot; i0 += U * NT) {
     int64_t g[U], zo[U];
     int32_t yv[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * kExecThreads;
+      const int i = i0 + u * NT;
       int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
       ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
       if (!ok[u]) {
@@ -153,18 +171,19 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, int
       if (PASS != kQ1 && ok[u]) stv(zp, zbits, zo[u], v);
     }
   }
-  ex_finish(E, ma.lm[ma.s[kOpZ]]);
+  ex_finish<NT>(E, ma.lm[ma.s[kOpZ]]);
 }
 
-template <int ND, int PASS, bool HASY>
-__device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, const LdsMeta& ma) {
-  const Src xs = src_of(L.x, L.xbits);
+template <int NT, int ND, int PASS, bool HASY>
+__device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, const LdsMeta& ma,
+                                     uintptr_t base) {
+  const Src xs = src_of(L.x, L.xbits, base);
   const int n = (int)L.n;
   const int64_t px = L.px, side = L.n + 2, zs = side * L.px;
   int32_t t[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) t[k] = L.taps[k];
-  ex_loop<ND, PASS, HASY, 4>(op, ma, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, 4>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t b = (ND == 3 ? (int64_t)z * side + y : (int64_t)y) * px + x;
     int64_t g = (int64_t)t[0] * ldx(xs, b) + (int64_t)t[1] * ldx(xs, b - 1) +
@@ -181,15 +200,16 @@ __device__ __forceinline__ constexpr int tidx(int iz, int iy, int ix) {
 }
 
 // restriction: z[I] = sum_o t[o] x[2I + o] over the 3^ND offsets
-template <int ND, int PASS, bool HASY>
-__device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma) {
-  const Src xs = src_of(L.x, L.xbits);
+template <int NT, int ND, int PASS, bool HASY>
+__device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma,
+                                     uintptr_t base) {
+  const Src xs = src_of(L.x, L.xbits, base);
   const int64_t px = L.px, sf = L.n_in + 2;
   int32_t t[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) t[k] = L.taps[k];
-  ex_loop<ND, PASS, HASY, ND == 3 ? 1 : 2>(op, ma, (int)L.n_out, L.y, L.ybits, L.py, L.z,
-                                           L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
+  ex_loop<NT, ND, PASS, HASY, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
+                                               L.py, L.z, L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
     int64_t g = 0;
 #pragma unroll
     for (int oz = (ND == 3 ? -1 : 0); oz <= (ND == 3 ? 1 : 0); ++oz)
@@ -209,15 +229,16 @@ __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArg
 // where along an even dimension only e = 0 contributes (offset 0) and along
 // an odd one e selects the offset 2e - 1. The tap of each corner is chosen
 // from the parities with selects, so the loads stay branch-free.
-template <int ND, int PASS, bool HASY>
-__device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma) {
-  const Src xs = src_of(L.x, L.xbits);
+template <int NT, int ND, int PASS, bool HASY>
+__device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma,
+                                     uintptr_t base) {
+  const Src xs = src_of(L.x, L.xbits, base);
   const int64_t px = L.px, sc = L.n_in + 2;
   int32_t t[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) t[k] = L.taps[k];
-  ex_loop<ND, PASS, HASY, ND == 3 ? 1 : 2>(op, ma, (int)L.n_out, L.y, L.ybits, L.py, L.z,
-                                           L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
+  ex_loop<NT, ND, PASS, HASY, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
+                                               L.py, L.z, L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
     const int qz = z & 1, qy = y & 1, qx = x & 1;
     const int jz = z >> 1, jy = y >> 1, jx = x >> 1;
     int64_t g = 0;
@@ -247,21 +268,23 @@ __device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs
   });
 }
 
-template <int ND, int PASS, bool HASY>
-__device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op, const LdsMeta& ma) {
-  const Src xs = src_of(L.x, L.xbits);
+template <int NT, int ND, int PASS, bool HASY>
+__device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op, const LdsMeta& ma,
+                                     uintptr_t base) {
+  const Src xs = src_of(L.x, L.xbits, base);
   const int64_t px = L.px, side = L.n + 2;
-  ex_loop<ND, PASS, HASY, 4>(op, ma, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, 4>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
     return ldx(xs, row * px + x);
   });
 }
 
-__device__ __forceinline__ void ex_zero(const ZeroOp& Z, int64_t* zm) {
-  uint4* p = static_cast<uint4*>(Z.mant);
+template <int NT>
+__device__ __forceinline__ void ex_zero(const ZeroOp& Z, int64_t* zm, uintptr_t base) {
+  uint4* p = static_cast<uint4*>(rel(Z.mant, base));
   const int64_t n16 = Z.bytes / 16;
-  for (int64_t i = threadIdx.x; i < n16; i += kExecThreads) p[i] = make_uint4(0, 0, 0, 0);
+  for (int64_t i = threadIdx.x; i < n16; i += NT) p[i] = make_uint4(0, 0, 0, 0);
   if (threadIdx.x < kExMetaF)
     zm[threadIdx.x] = threadIdx.x == kMetaExp ? Z.exp : (threadIdx.x == kMetaMu ? 1 : 0);
 }
@@ -272,34 +295,132 @@ __device__ __forceinline__ OpArgs with_mode(const OpArgs& a, int mode) {
   return op;
 }
 
-template <int ND, int PASS, bool HASY>
-__device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, int mode) {
+template <int NT, int ND, int PASS, bool HASY>
+__device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, int mode,
+                                            uintptr_t base) {
   const LdsMeta ma = lds_meta(lm, op.slot);
   if (op.kind == kExStar) {
-    ex_star<ND, PASS, HASY>(op.u.star, with_mode(op.u.star.op, mode), ma);
+    ex_star<NT, ND, PASS, HASY>(op.u.star, with_mode(op.u.star.op, mode), ma, base);
   } else if (op.kind == kExPoint) {
-    ex_point<ND, PASS, HASY>(op.u.pt, with_mode(op.u.pt.op, mode), ma);
+    ex_point<NT, ND, PASS, HASY>(op.u.pt, with_mode(op.u.pt.op, mode), ma, base);
   } else {
     const OpArgs a = with_mode(op.u.tr.op, mode);
-    if (op.u.tr.kind == 1) ex_restrict<ND, PASS, HASY>(op.u.tr, a, ma);
-    else ex_prolong<ND, PASS, HASY>(op.u.tr, a, ma);
+    if (op.u.tr.kind == 1) ex_restrict<NT, ND, PASS, HASY>(op.u.tr, a, ma, base);
+    else ex_prolong<NT, ND, PASS, HASY>(op.u.tr, a, ma, base);
+  }
+}
+
+// FP64 -> BFP (normalized floor quantization, the bfp_vec_from_f64
+// result): the largest nu(x_i) over the interior, then
+// m_i = floor(x_i / 2^(max nu - w)), exponent max nu - w + log2_scale.
+__device__ __forceinline__ bool f64_split(double x, int64_t& z, int64_t& e, bool& finite) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const int64_t E = (int64_t)((b >> 52) & 0x7FF);
+  const int64_t F = (int64_t)(b & ((1ull << 52) - 1));
+  finite = E != 0x7FF;
+  if (!finite || (E == 0 && F == 0)) return false;
+  const int64_t M = E ? (F | (1ll << 52)) : F;
+  e = E ? E - 1075 : -1074;
+  z = (b >> 63) ? -M : M;
+  return true;
+}
+
+template <int NT, int ND>
+__device__ __forceinline__ void ex_conv(const ConvOp& C, MetaRow& zm, uintptr_t base,
+                                        const double* const* rhs) {
+  __shared__ int32_t cred[3][NT / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const BFP_GLOBAL double* src =
+      (const BFP_GLOBAL double*)(C.src ? (const void*)C.src : (const void*)rhs[C.level - 1]);
+  const int n = (int)C.n;
+  const int64_t side = C.n + 2;
+  int lg = 0;
+  while ((1 << lg) < n) ++lg;
+  const int M = (1 << lg) - 1;
+  const int tot = ND == 3 ? 1 << (3 * lg) : 1 << (2 * lg);
+  // pass 1: max nu and the non-finite flag
+  int32_t best = INT32_MIN, bad = 0;
+  for (int i = t; i < tot; i += NT) {
+    const int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
+    if (x > n || y > n || (ND == 3 && z > n)) continue;
+    const int64_t idx = (ND == 3 ? (int64_t)z * side + y : (int64_t)y) * side + x;
+    int64_t zz, e;
+    bool fin;
+    if (f64_split(src[idx], zz, e, fin)) {
+      const int32_t nu = (int32_t)(msb64(zz) + e);
+      best = nu > best ? nu : best;
+    }
+    bad |= !fin;
+  }
+  best = wave_max32(best);
+  bad = wave_max32(bad);
+  if (lane == 0) {
+    cred[0][wave] = best;
+    cred[1][wave] = bad;
+  }
+  __syncthreads();
+  int32_t numax = INT32_MIN, anybad = 0;
+  for (int k = 0; k < NT / 64; ++k) {
+    numax = cred[0][k] > numax ? cred[0][k] : numax;
+    anybad |= cred[1][k];
+  }
+  const int64_t eq = numax == INT32_MIN ? 1 - C.w : (int64_t)numax - C.w;
+  // pass 2: quantize and store
+  void* mant = rel(C.mant, base);
+  int32_t tmax = 0, tmin = 0;
+  for (int i = t; i < tot; i += NT) {
+    const int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
+    if (x > n || y > n || (ND == 3 && z > n)) continue;
+    const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
+    int64_t zz, e, v = 0;
+    bool fin;
+    if (f64_split(src[row * side + x], zz, e, fin)) {
+      const int64_t sh = e - eq;
+      v = sh >= 0 ? (int64_t)((uint64_t)zz << sh) : shr_floor(zz, -sh);
+    }
+    tmax = (int32_t)v > tmax ? (int32_t)v : tmax;
+    tmin = (int32_t)v < tmin ? (int32_t)v : tmin;
+    stv(mant, C.bits, row * C.pitch + x, v);
+  }
+  tmax = wave_max32(tmax);
+  tmin = wave_min32(tmin);
+  __syncthreads();   // cred is reused
+  if (lane == 0) {
+    cred[0][wave] = tmax;
+    cred[1][wave] = tmin;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int32_t mx = 0, mn = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+      mx = cred[0][k] > mx ? cred[0][k] : mx;
+      mn = cred[1][k] < mn ? cred[1][k] : mn;
+    }
+    zm[kMetaExp] = eq + C.log2_scale;
+    zm[kMetaMax] = mx;
+    zm[kMetaMin] = mn;
+    zm[kMetaSat] = 0;
+    zm[kMetaMu] = numax == INT32_MIN ? INT64_MIN : (int64_t)numax;
+    zm[kMetaFlags] |= anybad;
   }
 }
 
 constexpr int kOpWords = (int)(sizeof(ExecOp) / 4);
-static_assert(sizeof(ExecOp) % 4 == 0 && kOpWords <= kExecThreads, "ExecOp copy layout");
+static_assert(sizeof(ExecOp) % 4 == 0 && kOpWords <= kBatchThreads, "ExecOp copy layout");
 
-template <int ND>
-__global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict__ ops, int count,
-                                                      int64_t* const* __restrict__ metas,
-                                                      int nmeta) {
+// Run one program (ops[0..count), metadata table metas[0..nmeta)) with this
+// workgroup; pointers are relocated by `base`.
+template <int NT, int ND>
+__device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int count,
+                                            int64_t* const* __restrict__ metas, int nmeta,
+                                            uintptr_t base, const double* const* rhs) {
   __shared__ MetaRow lm[kExecMaxMeta];
   __shared__ ExecOp buf[2];
   const int t = threadIdx.x;
   const uint32_t* gw = reinterpret_cast<const uint32_t*>(ops);
   uint32_t* bw = reinterpret_cast<uint32_t*>(buf);
-  if (t < nmeta * kExMetaF)
-    lm[t / kExMetaF][t % kExMetaF] = ((const BFP_GLOBAL int64_t*)metas[t / kExMetaF])[t % kExMetaF];
+  for (int i = t; i < nmeta * kExMetaF; i += NT)
+    lm[i / kExMetaF][i % kExMetaF] = ((const BFP_GLOBAL int64_t*)rel(metas[i / kExMetaF], base))[i % kExMetaF];
   if (t < kOpWords) bw[t] = gw[t];
   __syncthreads();
   for (int k = 0; k < count; ++k) {
@@ -308,33 +429,64 @@ __global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict_
     const uint32_t nextw = pre ? gw[(int64_t)(k + 1) * kOpWords + t] : 0;
     const ExecOp& op = buf[k & 1];
     if (op.kind == kExZero) {
-      ex_zero(op.u.zero, lm[op.slot[2]]);
+      ex_zero<NT>(op.u.zero, lm[op.slot[2]], base);
+    } else if (op.kind == kExConv) {
+      ex_conv<NT, ND>(op.u.conv, lm[op.slot[2]], base, rhs);
     } else {
       const int hasy = op.kind == kExStar ? op.u.star.op.has_y
                                           : (op.kind == kExPoint ? op.u.pt.op.has_y
                                                                  : op.u.tr.op.has_y);
       if (op.mode == kExModeQ) {
         if (hasy) {
-          ex_dispatch<ND, kQ1, true>(op, lm, kModeQ1);
-          ex_dispatch<ND, kOut, true>(op, lm, kModeQ2);
+          ex_dispatch<NT, ND, kQ1, true>(op, lm, kModeQ1, base);
+          ex_dispatch<NT, ND, kOut, true>(op, lm, kModeQ2, base);
         } else {
-          ex_dispatch<ND, kQ1, false>(op, lm, kModeQ1);
-          ex_dispatch<ND, kOut, false>(op, lm, kModeQ2);
+          ex_dispatch<NT, ND, kQ1, false>(op, lm, kModeQ1, base);
+          ex_dispatch<NT, ND, kOut, false>(op, lm, kModeQ2, base);
         }
       } else if (hasy) {
-        ex_dispatch<ND, kOut, true>(op, lm, op.mode);
+        ex_dispatch<NT, ND, kOut, true>(op, lm, op.mode, base);
       } else {
-        ex_dispatch<ND, kOut, false>(op, lm, op.mode);
+        ex_dispatch<NT, ND, kOut, false>(op, lm, op.mode, base);
       }
     }
     if (pre) bw[((k + 1) & 1) * kOpWords + t] = nextw;
     __syncthreads();
   }
-  if (t < nmeta * kExMetaF)
-    ((BFP_GLOBAL int64_t*)metas[t / kExMetaF])[t % kExMetaF] = lm[t / kExMetaF][t % kExMetaF];
+  for (int i = t; i < nmeta * kExMetaF; i += NT)
+    ((BFP_GLOBAL int64_t*)rel(metas[i / kExMetaF], base))[i % kExMetaF] = lm[i / kExMetaF][i % kExMetaF];
+}
+
+template <int ND>
+__global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict__ ops, int count,
+                                                      int64_t* const* __restrict__ metas,
+                                                      int nmeta) {
+  run_program<kExecThreads, ND>(ops, count, metas, nmeta, 0, nullptr);
+}
+
+template <int ND>
+__global__ __launch_bounds__(kBatchThreads) void k_exec_batch(
+    const BatchEntry* __restrict__ entries, const ExecOp* __restrict__ ops,
+    int64_t* const* __restrict__ metas, const double* const* __restrict__ rhs_table) {
+  const BatchEntry& E = entries[blockIdx.x];
+  run_program<kBatchThreads, ND>(ops + E.op_begin, E.op_count, metas + E.meta_begin, E.nmeta,
+                                 E.base, rhs_table + (int64_t)E.prob * kMaxLevels);
 }
 
 }  // namespace
+
+hipError_t launch_exec_batch(const BatchEntry* entries_dev, int nentries, const ExecOp* ops_dev,
+                             int64_t* const* metas_dev, const double* const* rhs_table_dev,
+                             int ndim, hipStream_t s) {
+  if (nentries <= 0) return hipSuccess;
+  if (ndim == 2)
+    hipLaunchKernelGGL(k_exec_batch<2>, dim3(nentries), dim3(kBatchThreads), 0, s, entries_dev,
+                       ops_dev, metas_dev, rhs_table_dev);
+  else
+    hipLaunchKernelGGL(k_exec_batch<3>, dim3(nentries), dim3(kBatchThreads), 0, s, entries_dev,
+                       ops_dev, metas_dev, rhs_table_dev);
+  return hipGetLastError();
+}
 
 hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_dev, int nmeta,
                        int ndim, hipStream_t s) {

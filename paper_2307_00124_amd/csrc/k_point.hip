@@ -235,6 +235,29 @@ hipError_t launch_init(void* mant, size_t bytes, int64_t* meta, int64_t exp, hip
   return hipGetLastError();
 }
 
+// one block per metadata block of a list: exponent exps[b], identities elsewhere
+__global__ void k_meta_init_list(int64_t* const* metas, const int64_t* exps) {
+  int64_t* m = metas[blockIdx.x];
+  const int i = threadIdx.x;
+  if (i >= kMetaSlots) return;
+  int64_t v = 0;
+  if (i >= kSetBase) {
+    const int f = (i - kSetBase) % kSetStride;
+    v = f == kAccMax ? INT64_MIN : (f == kAccMin ? INT64_MAX : 0);
+  } else if (i < kMetaTicket) {
+    v = i == kMetaExp ? exps[blockIdx.x] : (i == kMetaMu ? 1 : 0);
+  }
+  m[i] = v;
+}
+
+hipError_t launch_meta_init_list(int64_t* const* metas_dev, const int64_t* exps_dev, int count,
+                                 hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_meta_init_list, dim3((unsigned)count), dim3(kMetaSlots), 0, s, metas_dev,
+                     exps_dev);
+  return hipGetLastError();
+}
+
 hipError_t launch_meta_reset(int64_t* meta, hipStream_t s) {
   hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(kMetaSlots), 0, s, meta, (int64_t)0, 0);
   return hipGetLastError();

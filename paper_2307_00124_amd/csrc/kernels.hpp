@@ -75,6 +75,9 @@ hipError_t launch_from_f64(const ConvertLaunch& L, hipStream_t s);
 hipError_t launch_to_f64(const ConvertLaunch& L, hipStream_t s);
 hipError_t launch_init(void* mant, size_t bytes, int64_t* meta, int64_t exp, hipStream_t s);
 hipError_t launch_meta_reset(int64_t* meta, hipStream_t s);
+// initialise count metadata blocks (exponent exps[i], identities elsewhere)
+hipError_t launch_meta_init_list(int64_t* const* metas_dev, const int64_t* exps_dev, int count,
+                                 hipStream_t s);
 
 struct DotLaunch {
   const void* x;
@@ -90,7 +93,7 @@ hipError_t launch_dot(const DotLaunch& L, hipStream_t s);
 
 // One recorded operation of a coarse-level program (see k_exec.hip): the
 // launch description the library would otherwise launch, and its mode.
-constexpr int kExStar = 1, kExTransfer = 2, kExPoint = 3, kExZero = 4;
+constexpr int kExStar = 1, kExTransfer = 2, kExPoint = 3, kExZero = 4, kExConv = 5;
 constexpr int kExModeQ = 9;   // both qcomp passes, executed back to back
 
 // bfp_vec_init inside a program: zero mantissas, exponent 1 - w
@@ -99,6 +102,20 @@ struct ZeroOp {
   int64_t* meta;
   int64_t bytes;   // multiple of 16
   int64_t exp;
+};
+
+// bfp_vec_from_f64 inside a program: the FP64 source is `src`, or, when
+// src is null, entry `level` - 1 of the running problem's right-hand-side
+// table (batched solves)
+struct ConvOp {
+  const double* src;
+  void* mant;
+  int64_t* meta;
+  int ndim;
+  int64_t n, pitch;
+  int bits, w;
+  int64_t log2_scale;
+  int level;
 };
 
 struct ExecOp {
@@ -112,6 +129,7 @@ struct ExecOp {
     TransferLaunch tr;
     PointLaunch pt;
     ZeroOp zero;
+    ConvOp conv;
   } u;
 };
 
@@ -126,5 +144,22 @@ constexpr int kExecMaxMeta = 64;
 constexpr int kExMetaF = 8;
 hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_dev, int nmeta,
                        int ndim, hipStream_t s);
+
+// Batched programs: one workgroup of kBatchThreads threads per problem runs
+// that problem's program. Programs are relocatable: every data and metadata
+// pointer in their ops and metadata tables is an offset from the problem's
+// arena base. rhs_table[p * kMaxLevels + j - 1] is problem p's FP64
+// right-hand side on level j.
+constexpr int kBatchThreads = 256;
+constexpr int kMaxLevels = 16;
+struct BatchEntry {
+  uintptr_t base;        // the problem's arena base
+  int prob;              // row of the right-hand-side table
+  int op_begin, op_count;
+  int meta_begin, nmeta; // the program's metadata table (offsets)
+};
+hipError_t launch_exec_batch(const BatchEntry* entries_dev, int nentries, const ExecOp* ops_dev,
+                             int64_t* const* metas_dev, const double* const* rhs_table_dev,
+                             int ndim, hipStream_t s);
 
 }  // namespace bfpk

@@ -408,6 +408,138 @@ int count_ops(const mg_params* prm, size_t* nops) {
   return rc;
 }
 
+// ------------------------------------------------------------ batches ---
+//
+// A batch holds many independent problems, each with its own hierarchy in
+// the batch arena. Problems with identical parameters share one recorded,
+// relocatable program: the conversion of the right-hand side on every level
+// followed by the whole FMG, with every data and metadata pointer stored as
+// an offset from the problem's arena base. One launch runs every problem's
+// program, one workgroup per problem.
+
+constexpr uintptr_t kStandIn = (uintptr_t)1 << 20;   // recording base of a program
+
+struct BatchGroup {
+  mg_params prm;
+  mg_hierarchy* h;              // laid out at kStandIn
+  std::vector<ExecOp> ops;      // relocated
+  std::vector<int64_t*> metas;  // relocated
+  size_t region;                // bytes of one problem's hierarchy
+  double bytes;                 // algorithmic bytes of one solve
+};
+
+template <typename P>
+void unbase(P*& p) {
+  if (p) p = (P*)((uintptr_t)p - kStandIn);
+}
+
+int record_batch_program(BatchGroup& g) {
+  mg_hierarchy* h = g.h;
+  const mg_params& p = g.prm;
+  g.ops.clear();
+  const double b0 = h->bytes;
+  for (int j = 1; j <= p.L; ++j) {
+    const bfp_vec& b = h->lv[j].b;
+    ExecOp e;
+    std::memset(&e, 0, sizeof e);
+    e.kind = kExConv;
+    e.u.conv = ConvOp{nullptr, b.mant, b.meta, b.ndim, b.n, b.pitch, b.storage_bits, b.w,
+                      (int64_t)(p.ndim == 2 ? -2 * j - 2 : -2 * j - 3), j};
+    g.ops.push_back(e);
+    h->bytes += pts(b) * (8.0 + sz(b));
+  }
+  record_into(&g.ops);
+  int rc = fmg_levels(h, 1, p.L, nullptr);
+  record_into(nullptr);
+  g.bytes = h->bytes - b0;
+  h->bytes = b0;
+  if (rc) return rc;
+  if ((rc = exec_assign_slots(g.ops, g.metas))) return rc;
+  for (ExecOp& e : g.ops) {
+    switch (e.kind) {
+      case kExStar: unbase(e.u.star.x); unbase(e.u.star.y); unbase(e.u.star.z); break;
+      case kExTransfer: unbase(e.u.tr.x); unbase(e.u.tr.y); unbase(e.u.tr.z); break;
+      case kExPoint: unbase(e.u.pt.x); unbase(e.u.pt.y); unbase(e.u.pt.z); break;
+      case kExZero: unbase(e.u.zero.mant); break;
+      case kExConv: unbase(e.u.conv.mant); break;
+    }
+  }
+  for (int64_t*& m : g.metas) unbase(m);
+  return BFP_OK;
+}
+
+}  // namespace
+
+struct mg_batch {
+  int nprob = 0, ndim = 0;
+  std::vector<BatchGroup> groups;
+  std::vector<int> group_of;        // per problem
+  std::vector<uintptr_t> base;      // per problem
+  BatchEntry* entries = nullptr;    // device, in launch order
+  ExecOp* ops = nullptr;            // device
+  int64_t** metas = nullptr;        // device
+  double bytes = 0;                 // algorithmic bytes of one batched solve
+  int64_t launches = 0;
+  ~mg_batch() {
+    for (BatchGroup& g : groups) delete g.h;
+  }
+};
+
+namespace {
+
+// Plan a batch: groups, programs, and the arena layout (base = null: sizes only).
+int plan_batch(mg_batch* B, const mg_params* prms, int nprob, char* arena, size_t* total) {
+  if (!prms || nprob < 1) return fail(BFP_EINVAL, "need at least one problem");
+  B->nprob = nprob;
+  B->ndim = prms[0].ndim;
+  for (BatchGroup& g : B->groups) delete g.h;
+  B->groups.clear();
+  B->group_of.assign(nprob, -1);
+  for (int i = 0; i < nprob; ++i) {
+    int rc = check_params(&prms[i]);
+    if (rc) return rc;
+    if (prms[i].ndim != B->ndim) return fail(BFP_ESHAPE, "every problem of a batch needs the same ndim");
+    const int64_t n = ((int64_t)1 << prms[i].L) - 1;
+    if (n >= kExecMaxN) return fail(BFP_ESHAPE, "problem %d: batched grids need n < %d", i, kExecMaxN);
+    int gi = -1;
+    for (size_t k = 0; k < B->groups.size(); ++k)
+      if (!std::memcmp(&B->groups[k].prm, &prms[i], sizeof(mg_params))) { gi = (int)k; break; }
+    if (gi < 0) {
+      BatchGroup g;
+      g.prm = prms[i];
+      g.h = new (std::nothrow) mg_hierarchy();
+      if (!g.h) return fail(BFP_ENOMEM, "host allocation failed");
+      B->groups.push_back(g);
+      gi = (int)B->groups.size() - 1;
+      BatchGroup& G = B->groups.back();
+      if ((rc = setup(G.h, &G.prm))) return rc;
+      G.h->Lc = 0;
+      G.region = layout(G.h, &G.prm, reinterpret_cast<char*>(kStandIn), 0);
+      if ((rc = record_batch_program(G))) return rc;
+    }
+    B->group_of[i] = gi;
+  }
+  size_t off = 0;
+  const size_t ent = align256(nprob * sizeof(BatchEntry));
+  size_t nops = 0, nmeta = 0;
+  for (BatchGroup& g : B->groups) { nops += g.ops.size(); nmeta += g.metas.size(); }
+  B->entries = arena ? (BatchEntry*)(arena + off) : nullptr;
+  off += ent;
+  B->metas = arena ? (int64_t**)(arena + off) : nullptr;
+  off = align256(off + nmeta * sizeof(int64_t*));
+  B->ops = arena ? (ExecOp*)(arena + off) : nullptr;
+  off = align256(off + nops * sizeof(ExecOp));
+  B->base.assign(nprob, 0);
+  B->bytes = 0;
+  for (int i = 0; i < nprob; ++i) {
+    B->base[i] = arena ? (uintptr_t)(arena + off) : 0;
+    off = align256(off + B->groups[B->group_of[i]].region);
+    B->bytes += B->groups[B->group_of[i]].bytes;
+  }
+  *total = off;
+  return BFP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -627,4 +759,118 @@ int mg_counters(const mg_hierarchy* h, double* bytes, int64_t* launches) {
   return BFP_OK;
 }
 
+size_t mg_batch_bytes(const mg_params* prms, int nprob) {
+  mg_batch B;
+  size_t total = 0;
+  if (plan_batch(&B, prms, nprob, nullptr, &total)) return 0;
+  return total;
+}
+
+int mg_batch_create(const mg_params* prms, int nprob, void* arena_dev, size_t bytes,
+                    void* stream, mg_batch** out) {
+  if (!out || !arena_dev) return fail(BFP_EINVAL, "NULL argument");
+  if ((uintptr_t)arena_dev % 256) return fail(BFP_EINVAL, "arena must be 256-byte aligned");
+  mg_batch* B = new (std::nothrow) mg_batch();
+  if (!B) return fail(BFP_ENOMEM, "host allocation failed");
+  size_t need = 0;
+  int rc = plan_batch(B, prms, nprob, nullptr, &need);
+  if (!rc && bytes < need)
+    rc = fail(BFP_ENOMEM, "arena holds %zu bytes, the batch needs %zu", bytes, need);
+  if (!rc) rc = plan_batch(B, prms, nprob, static_cast<char*>(arena_dev), &need);
+  if (rc) { delete B; return rc; }
+  hipStream_t s = (hipStream_t)stream;
+  // device tables: entries (largest programs first), metadata tables, ops
+  std::vector<ExecOp> ops;
+  std::vector<int64_t*> metas;
+  std::vector<int> op_begin(B->groups.size()), meta_begin(B->groups.size());
+  for (size_t k = 0; k < B->groups.size(); ++k) {
+    op_begin[k] = (int)ops.size();
+    meta_begin[k] = (int)metas.size();
+    ops.insert(ops.end(), B->groups[k].ops.begin(), B->groups[k].ops.end());
+    metas.insert(metas.end(), B->groups[k].metas.begin(), B->groups[k].metas.end());
+  }
+  std::vector<BatchEntry> ent(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const int k = B->group_of[i];
+    ent[i] = BatchEntry{B->base[i], i, op_begin[k], (int)B->groups[k].ops.size(), meta_begin[k],
+                        (int)B->groups[k].metas.size()};
+  }
+  std::stable_sort(ent.begin(), ent.end(),
+                   [](const BatchEntry& a, const BatchEntry& b) { return a.op_count > b.op_count; });
+  // initial state: zero mantissas, metadata at exponent 1 - w with identities
+  std::vector<int64_t*> mlist;
+  std::vector<int64_t> elist;
+  for (int i = 0; i < nprob; ++i) {
+    const BatchGroup& g = B->groups[B->group_of[i]];
+    for (int j = 1; j <= g.prm.L; ++j) {
+      const Level& L = g.h->lv[j];
+      for (const bfp_vec* v : {&L.x, &L.b, &L.r, &L.vr, &L.y, &L.s, &L.t}) {
+        mlist.push_back((int64_t*)((uintptr_t)v->meta - kStandIn + B->base[i]));
+        elist.push_back(1 - v->w);
+      }
+    }
+  }
+  char* first = (char*)B->base[0];
+  const size_t region_bytes = (size_t)((char*)arena_dev + need - first);
+  void* scratch = nullptr;
+  const size_t lists = mlist.size() * (sizeof(int64_t*) + sizeof(int64_t));
+  rc = hip_check(hipMemsetAsync(first, 0, region_bytes, s), "batch arena clear");
+  if (!rc) rc = hip_check(hipMalloc(&scratch, lists), "batch set-up buffer");
+  if (!rc) rc = hip_check(hipMemcpyAsync(scratch, mlist.data(), mlist.size() * sizeof(int64_t*),
+                                         hipMemcpyHostToDevice, s), "batch set-up copy");
+  int64_t* exps_dev = scratch ? (int64_t*)((char*)scratch + mlist.size() * sizeof(int64_t*)) : nullptr;
+  if (!rc) rc = hip_check(hipMemcpyAsync(exps_dev, elist.data(), elist.size() * sizeof(int64_t),
+                                         hipMemcpyHostToDevice, s), "batch set-up copy");
+  if (!rc) rc = hip_check(launch_meta_init_list((int64_t* const*)scratch, exps_dev,
+                                                (int)mlist.size(), s), "batch metadata init");
+  if (!rc) rc = hip_check(hipMemcpyAsync(B->entries, ent.data(), ent.size() * sizeof(BatchEntry),
+                                         hipMemcpyHostToDevice, s), "batch upload");
+  if (!rc && !metas.empty())
+    rc = hip_check(hipMemcpyAsync(B->metas, metas.data(), metas.size() * sizeof(int64_t*),
+                                  hipMemcpyHostToDevice, s), "batch upload");
+  if (!rc) rc = hip_check(hipMemcpyAsync(B->ops, ops.data(), ops.size() * sizeof(ExecOp),
+                                         hipMemcpyHostToDevice, s), "batch upload");
+  const int rs = hip_check(hipStreamSynchronize(s), "batch upload");
+  if (!rc) rc = rs;
+  if (scratch) hipFree(scratch);
+  if (rc) { delete B; return rc; }
+  *out = B;
+  return BFP_OK;
+}
+
+int mg_batch_destroy(mg_batch* b) {
+  delete b;
+  return BFP_OK;
+}
+
+int mg_solve_batch(mg_batch* b, const double* const* rhs_table_dev, void* stream) {
+  if (!b || !rhs_table_dev) return fail(BFP_EINVAL, "NULL argument");
+  int rc = hip_check(launch_exec_batch(b->entries, b->nprob, b->ops, b->metas, rhs_table_dev,
+                                       b->ndim, (hipStream_t)stream), "batched solve");
+  if (rc) return rc;
+  b->launches += 1;
+  return BFP_OK;
+}
+
+int mg_batch_get_vec(mg_batch* b, int prob, int level, int which, bfp_vec* out) {
+  if (!b || !out || prob < 0 || prob >= b->nprob) return fail(BFP_EINVAL, "bad argument");
+  const BatchGroup& g = b->groups[b->group_of[prob]];
+  if (level < 1 || level > g.prm.L) return fail(BFP_EINVAL, "bad level");
+  const Level& L = g.h->lv[level];
+  const bfp_vec* v = which == 0 ? &L.x : which == 1 ? &L.b : which == 2 ? &L.r : which == 3 ? &L.y : nullptr;
+  if (!v) return fail(BFP_EINVAL, "unknown block %d", which);
+  *out = *v;
+  out->mant = (void*)((uintptr_t)v->mant - kStandIn + b->base[prob]);
+  out->meta = (int64_t*)((uintptr_t)v->meta - kStandIn + b->base[prob]);
+  return BFP_OK;
+}
+
+int mg_batch_counters(const mg_batch* b, double* bytes, int64_t* launches) {
+  if (!b) return fail(BFP_EINVAL, "NULL batch");
+  if (bytes) *bytes = b->bytes;
+  if (launches) *launches = b->launches;
+  return BFP_OK;
+}
+
 }  // extern "C"
+static_assert(bfpk::kMaxLevels == MG_MAX_LEVELS, "right-hand-side table rows");

@@ -8,13 +8,17 @@ IR-V(1,0) iterations per level on 12 levels with progressive widths
 qcomp), then the normalized BFP solution and the exact dot product of the
 final residual. Prints one JSON line.
 
-Also measured: the dominant kernel (the finest-level 5-point residual) timed
-with HIP events on the stream it runs on, the finest inner width sweep, the
-discretization-accuracy gate, and the CPU oracle on a bounded sample.
+Also measured (extra keys of the same line): the dominant kernel (the
+finest-level 5-point residual) timed with HIP events on the stream it runs
+on, the plain 5-point and 7-point stencil applies (4095^2 and 511^3, int32),
+the finest inner width sweep, the discretization-accuracy gate, the batched
+workload (4096 independent 2D solves of sides 33..257 in one launch) against
+a one-solve-at-a-time loop, and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -25,6 +29,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs, valid while the kernel sources hash to the recorded value
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "residual_4095sq_traffic.json")
+KERNEL_SOURCES = ["common.hpp", "device.hpp", "epilogue.hpp", "kernels.hpp", "star_impl.hpp",
+                  "k_star_x32.hip", "k_star.hip"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2307_00124_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -38,6 +55,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-level", type=int, default=10)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--batch", type=int, default=4096, help="problems of the batched leg (0: skip)")
+    ap.add_argument("--loop-sample", type=int, default=32,
+                    help="problems solved one at a time for the batched comparison")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--only", choices=["all", "kernel", "copy"], default="all",
+                    help="kernel: only the dominant-kernel loop (for profiler runs); copy: only "
+                         "a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -47,6 +71,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solves of "
               "this workload are single-GPU and no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
 
     import paper_2307_00124_amd as P
@@ -55,17 +80,61 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    if args.only == "copy":
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "launches": 5}))
+        return
+
     L = args.level
     n = (1 << L) - 1
     dof = n * n
+    A2 = P.Stencil(2, P.BFP_STENCIL_A, -2, [0, -1, 0, -1, 4, -1, 0, -1, 0], 4)
 
     def make(w):
         p = P.mg_params_init(2, L, w, True, 1, 0, 2, P.MG_POLICY_NN_IR_FIRST_Q, 23)
         p.min_storage_bits = 32
-        H = P.Hierarchy(p)
-        return H
+        return P.Hierarchy(p)
 
     f = [None] + [torch.from_numpy(W.manufactured_f(j, 2)).to(dev) for j in range(1, L + 1)]
+
+    def time_kernel(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        k0, k1 = ev(), ev()
+        k0.record(stream)
+        for _ in range(reps):
+            fn()
+        k1.record(stream)
+        torch.cuda.synchronize()
+        return k0.elapsed_time(k1) * 1000.0 / reps
+
+    # ----------------------------------- dominant kernel, HIP events ---
+    # the finest-level IR residual r = A x - b in saturate mode: the 5-point
+    # star kernel with a y stream, on the iterate of a finished solve (the
+    # same launch the FMG issues)
+    H = make(args.w)
+    for j in range(1, L + 1):
+        H.set_rhs(j, f[j], stream)
+    H.fmg(stream)
+    x, b, r = H.get_vec(L, 0), H.get_vec(L, 1), H.get_vec(L, 2)
+    g = P.gamma_norm(r)
+    kern_us = time_kernel(lambda: P.bfp_residual(A2, x, b, r.w, P.BFP_SATURATE, g, r, stream),
+                          args.kernel_reps)
+    kern_bytes = dof * (x.storage_bits + b.storage_bits + r.storage_bits) / 8.0
+    kern_gbs = kern_bytes / (kern_us * 1e-6) / 1e9
+    if args.only == "kernel":
+        print(json.dumps({"kernel": "residual 4095^2 int32", "avg_us": kern_us, "gbs": kern_gbs}))
+        return
+
     us = torch.from_numpy(W.manufactured_u(L, 2)).to(dev)
     h2 = 2.0 ** (-2 * L)
     kappa = (math.pi * 2.0 ** -L) ** 2 / (4.0 * math.sin(math.pi * 2.0 ** -L / 2.0) ** 2)
@@ -74,19 +143,18 @@ def main():
 
     def step(H, xout):
         for j in range(1, L + 1):
-            H.set_rhs(j, f[j], stream)                  # a1: FP64 -> BFP (b_j)
-        H.fmg(stream)                                   # a2-a13
-        x = H.get_vec(L, 0)
-        P.bfp_normalize(x, x.w, xout, stream)           # a7: normalized solution
-        r = H.get_vec(L, 2)
-        P.bfp_dot(r, r, dot_out, stream)                # a5: exact r.r
+            H.set_rhs(j, f[j], stream)                  # FP64 -> BFP (b_j)
+        H.fmg(stream)                                   # FMG
+        xl = H.get_vec(L, 0)
+        P.bfp_normalize(xl, xl.w, xout, stream)         # normalized solution
+        rl = H.get_vec(L, 2)
+        P.bfp_dot(rl, rl, dot_out, stream)              # exact r.r
 
     def timed(H, xout, steps, warmup):
         for _ in range(warmup):
             step(H, xout)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        e0, e1 = ev(), ev()
         e0.record(stream)
         for _ in range(steps):
             step(H, xout)
@@ -100,7 +168,6 @@ def main():
         return err / disc
 
     # ---------------------------------------------------------- main run --
-    H = make(args.w)
     xout = P.Vec(2, n, H.get_vec(L, 0).w, 32)
     ms = timed(H, xout, args.steps, args.warmup)
     ratio = accuracy(xout)
@@ -111,40 +178,53 @@ def main():
     step_bytes = bytes_after - bytes_before
     step_launches = launches_after - launches_before
 
-    # -------------------------------------- dominant kernel, HIP events ---
-    # the finest-level IR residual r = A x - b in saturate mode: the 5-point
-    # star kernel with a y stream, the same launch the FMG issues
-    x, b, r = H.get_vec(L, 0), H.get_vec(L, 1), H.get_vec(L, 2)
-    A = P.Stencil(2, P.BFP_STENCIL_A, -2, [0, -1, 0, -1, 4, -1, 0, -1, 0], 4)
-    g = P.gamma_norm(r)
-    for _ in range(3):
-        P.bfp_residual(A, x, b, r.w, P.BFP_SATURATE, g, r, stream)
-    torch.cuda.synchronize()
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    for _ in range(args.kernel_reps):
-        P.bfp_residual(A, x, b, r.w, P.BFP_SATURATE, g, r, stream)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kern_us = k0.elapsed_time(k1) * 1000.0 / args.kernel_reps
-    kern_bytes = dof * (x.storage_bits + b.storage_bits + r.storage_bits) / 8.0
-    kern_gbs = kern_bytes / (kern_us * 1e-6) / 1e9
-    # restore the solver state touched above
-    step(H, xout)
-    torch.cuda.synchronize()
+    # --------------------------------------- plain stencil applies ------
+    # z = A x (two int32 streams), 2D 4095^2 and 3D 511^3
+    stencils = {}
+    xs = P.Vec(2, n, 30, 32)
+    P.bfp_vec_from_f64(f[L], 0, xs, stream)
+    zs = P.Vec(2, n, 32, 32)
+    gz = P.gamma_norm(xs, P.scalar(1, 1))
+    t2 = time_kernel(lambda: P.bfp_stencil_apply(A2, xs, None, None, None, 32, P.BFP_SATURATE,
+                                                 gz, zs, stream), args.kernel_reps)
+    stencils["5pt_4095sq_int32"] = {"avg_us": round(t2, 2), "bytes": dof * 8.0,
+                                    "gbs": round(dof * 8.0 / (t2 * 1e-6) / 1e9, 1)}
+    del xs, zs
+    if not args.no_3d:
+        n3 = 511
+        A3 = P.Stencil(3, P.BFP_STENCIL_A, -3,
+                       [6 if k == 13 else (-1 if k in (4, 10, 12, 14, 16, 22) else 0)
+                        for k in range(27)], 4)
+        x3 = P.Vec(3, n3, 24, 32)
+        z3 = P.Vec(3, n3, 32, 32)
+        f3 = torch.from_numpy(W.manufactured_f(9, 3)).to(dev)
+        P.bfp_vec_from_f64(f3, 0, x3, stream)
+        del f3
+        g3 = P.gamma_norm(x3, P.scalar(1, 1))
+        t3 = time_kernel(lambda: P.bfp_stencil_apply(A3, x3, None, None, None, 32,
+                                                     P.BFP_SATURATE, g3, z3, stream), 20)
+        d3 = n3 ** 3
+        stencils["7pt_511cube_int32"] = {"avg_us": round(t3, 2), "bytes": d3 * 8.0,
+                                         "gbs": round(d3 * 8.0 / (t3 * 1e-6) / 1e9, 1)}
+        del x3, z3
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------ width sweep ---
     sweep = []
     for w in [int(s) for s in args.sweep.split(",") if s]:
         Hs = make(w)
-        xs = P.Vec(2, n, Hs.get_vec(L, 0).w, 32)
-        msw = timed(Hs, xs, 3, 1)
+        xw = P.Vec(2, n, Hs.get_vec(L, 0).w, 32)
+        msw = timed(Hs, xw, 3, 1)
+        acc = accuracy(xw)
         sweep.append({"w": w, "ms": round(msw, 3), "dof_per_s": dof / (msw * 1e-3),
-                      "err_over_disc": round(accuracy(xs), 4),
-                      "at_disc_error": accuracy(xs) <= 1.1})
-        del Hs, xs
+                      "err_over_disc": round(acc, 4), "at_disc_error": acc <= 1.1})
+        del Hs, xw
         torch.cuda.empty_cache()
+
+    # --------------------------------------------------- batched solves ---
+    batch = None
+    if args.batch > 0:
+        batch = bench_batch(args, P, W, np, torch, dev, stream, ev)
 
     # ---------------------------------------------------- CPU baseline ----
     cpu = None
@@ -164,6 +244,15 @@ def main():
                "sample": f"one FMG solve of the same method on the {(1 << Lc) + 1}^2 grid "
                          f"({Lc} levels, finest inner width {args.w}), exact Python integers, "
                          f"{t:.1f} s"}
+
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("source_sha256") == kernel_source_hash():
+            traffic = tr["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
 
     out = {
         "metric": "BFP-FMG DoF/s at discretization error vs FP64 MG; stencil GB/s; p99 latency",
@@ -186,14 +275,101 @@ def main():
                    "launches_per_step": step_launches,
                    "algorithmic_bytes_per_step": step_bytes},
         "roofline": {"bound": "hbm", "achieved": round(kern_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
                      "kernel": "k_star2d (5-point residual A x - b, int32, finest level)",
                      "avg_us": round(kern_us, 2), "bytes_per_launch": kern_bytes},
         "solve_algorithmic_gbs": step_bytes / (ms * 1e-3) / 1e9,
+        "stencil_apply": stencils,
         "sweep": sweep,
+        "batched": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def bench_batch(args, P, W, np, torch, dev, stream, ev):
+    """The batched workload: independent 2D solves (sides 33..257, 8 sine
+    modes, inner width 16 in int16, x and b in int32), all in one launch,
+    against the same kind of solves issued one at a time."""
+    solves = W.batch_trace(args.batch, seed=1)
+    prms = [P.batch_params(2, s.level, 16) for s in solves]
+    keep = {}
+    table = torch.zeros(len(solves) * P.MG_MAX_LEVELS, dtype=torch.int64)
+    for i, s in enumerate(solves):
+        for j in range(1, s.level + 1):
+            t = torch.from_numpy(np.ascontiguousarray(W.sine_f(j, s.modes))).to(dev)
+            keep[(i, j)] = t
+            table[i * P.MG_MAX_LEVELS + j - 1] = t.data_ptr()
+    table = table.to(dev)
+    B = P.Batch(prms)
+    dof = sum(((1 << s.level) - 1) ** 2 for s in solves)
+    for _ in range(2):
+        B.solve(table, stream)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        B.solve(table, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bytes_per, _ = B.counters()
+
+    # accuracy on a sample: error to the continuum solution against the FP64
+    # discrete solution's (closed form: sine modes are eigenvectors of A_h)
+    worst = 0.0
+    for i in range(0, len(solves), max(1, len(solves) // 16)):
+        s = solves[i]
+        j = s.level
+        hh = 2.0 ** -j
+        u = P.bfp_vec_to_f64(B.get_vec(i, j, 0)).cpu().numpy()
+        ue = W.sine_u(j, s.modes)
+        uh = np.zeros_like(ue)
+        xk = np.arange((1 << j) + 1) * hh
+        for (kx, ky), a in zip(s.modes.k, s.modes.a):
+            lam = (4.0 / hh ** 2) * (math.sin(kx * math.pi * hh / 2) ** 2 +
+                                     math.sin(ky * math.pi * hh / 2) ** 2)
+            uh += (a / lam) * np.outer(np.sin(ky * math.pi * xk), np.sin(kx * math.pi * xk))
+        e_bfp = math.sqrt(float(((u - ue)[1:-1, 1:-1] ** 2).sum()) * hh * hh)
+        e_fp = math.sqrt(float(((uh - ue)[1:-1, 1:-1] ** 2).sum()) * hh * hh)
+        worst = max(worst, e_bfp / e_fp)
+
+    # one solve at a time through the per-solve calls, on a sample holding
+    # every side equally
+    by_side = {}
+    for i, s in enumerate(solves):
+        by_side.setdefault(s.side, []).append(i)
+    per = max(1, args.loop_sample // len(by_side))
+    sample = [i for side in sorted(by_side) for i in by_side[side][:per]]
+    Hs = [P.Hierarchy(prms[i]) for i in sample]
+
+    def loop():
+        for Hh, i in zip(Hs, sample):
+            for j in range(1, solves[i].level + 1):
+                Hh.set_rhs(j, keep[(i, j)], stream)
+            Hh.fmg(stream)
+
+    loop()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    loop()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1)
+    loop_dof = sum(((1 << solves[i].level) - 1) ** 2 for i in sample)
+    loop_rate = loop_dof / (loop_ms * 1e-3)
+    rate = dof / (ms * 1e-3)
+    return {"workload": f"{len(solves)} independent 2D Poisson FMG solves, sides "
+                        "{33,65,129,257} (seed 1), 8 sine modes, N=2+max(0,L-6) IR-V(1,0) per "
+                        "level, inner w=16 int16, "
+                        "x and b int32, one launch", "dof": dof, "ms": round(ms, 3),
+            "dof_per_s": rate, "algorithmic_gbs": bytes_per / (ms * 1e-3) / 1e9,
+            "worst_err_over_disc_sampled": round(worst, 4),
+            "loop_dof_per_s": loop_rate, "loop_sample": len(sample),
+            "speedup_vs_loop": round(rate / loop_rate, 2)}
 
 
 if __name__ == "__main__":

@@ -363,7 +363,7 @@ def bench_batch(args, P, W, np, torch, dev, stream, ev):
     loop_rate = loop_dof / (loop_ms * 1e-3)
     rate = dof / (ms * 1e-3)
     return {"workload": f"{len(solves)} independent 2D Poisson FMG solves, sides "
-                        "{33,65,129,257} (seed 1), 8 sine modes, N=2+max(0,L-6) IR-V(1,0) per "
+                        "{33,65,129,257} (seed 1), 8 sine modes, N=max(2,L-3) IR-V(1,0) per "
                         "level, inner w=16 int16, "
                         "x and b int32, one launch", "dof": dof, "ms": round(ms, 3),
             "dof_per_s": rate, "algorithmic_gbs": bytes_per / (ms * 1e-3) / 1e9,

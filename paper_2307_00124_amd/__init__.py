@@ -419,10 +419,10 @@ def batch_params(ndim: int, L: int, w_inner: int = 16, nu1: int = 1, nu2: int = 
     min(32, 2j + 8), inner width min(working, w_inner) on every level. With a
     fixed inner width the V-cycle's correction is only that accurate, so
     reaching the discretization error takes more IR iterations per level as
-    the grid grows: N = 2 + max(0, L - 6) by default (2 up to 65^2, 3 at
-    129^2, 4 at 257^2 for w_inner = 16)."""
+    the grid grows: N = max(2, L - 3) by default (2 up to 65^2, 4 at 129^2,
+    5 at 257^2 for w_inner = 16)."""
     if N is None:
-        N = 2 + max(0, L - 6)
+        N = max(2, L - 3)
     p = mg_params_init(ndim, L, w_inner, True, nu1, nu2, N, policy, eta_percent)
     for j in range(1, L + 1):
         p.w_check[j] = 32

@@ -138,7 +138,7 @@ struct ExecOp {
 // metas[0..nmeta) are the metadata blocks the ops name by slot: the
 // executor works on an LDS copy of their first kExMetaF fields and writes
 // it back at the end.
-constexpr int kExecThreads = 1024;
+constexpr int kExecThreads = 512;
 constexpr int kExecMaxN = 1024;
 constexpr int kExecMaxMeta = 64;
 constexpr int kExMetaF = 8;

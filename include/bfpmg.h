@@ -340,6 +340,47 @@ int mg_batch_get_vec(mg_batch* b, int prob, int level, int which, bfp_vec* out);
 /* Algorithmic bytes of one mg_solve_batch and the launches issued so far.  */
 int mg_batch_counters(const mg_batch* b, double* bytes, int64_t* launches);
 
+/* ---------------------------------------------------------- serving ---
+ * A request server (the serving workload): independent solves of mixed
+ * dimensions, sizes and widths are submitted without blocking and run
+ * concurrently in up to max_slots execution slots (one HIP stream each,
+ * default priority). Each request needs a resident hierarchy for its
+ * parameters inside the caller's arena (the HBM budget): hierarchies are
+ * reused across requests with bitwise-identical parameters, created while
+ * the budget allows and evicted least-recently-used when idle; a request
+ * waits while neither a slot nor memory is free (admission in arrival
+ * order). A slot runs the whole solve: mg_set_rhs on every level, mg_fmg,
+ * and the finest iterate converted to FP64 into x_out_dev. Results are
+ * bit-identical to the same solve run alone. Hierarchy creation on first
+ * use of a parameter set synchronizes that slot's stream. Not thread-safe:
+ * one host thread drives a server.                                       */
+typedef struct mg_server mg_server;
+typedef struct {
+  int32_t max_slots;   /* requests on the device at once, 1..64            */
+  int32_t max_queue;   /* queued requests beyond which submit is BFP_EBUSY  */
+} mg_server_cfg;
+typedef struct {
+  mg_params prm;                          /* shape, widths, schedule       */
+  const double* rhs_dev[MG_MAX_LEVELS];   /* [j-1]: FP64 f_j on the padded
+                                             level-j grid (device); must stay
+                                             valid until the request is done */
+  double* x_out_dev;                      /* (2^L + 1)^ndim FP64 values     */
+} mg_request;
+typedef struct {
+  int32_t status;      /* BFP_OK or the error that ended the request        */
+  float gpu_ms;        /* device time from the request's first to last op   */
+} mg_result;
+
+int mg_server_create(const mg_server_cfg* cfg, void* arena_dev, size_t bytes, mg_server** out);
+/* Queue a request (non-blocking); BFP_EBUSY when the queue is full.       */
+int mg_server_submit(mg_server* s, const mg_request* req, uint64_t* ticket);
+/* Make progress (retire finished slots, admit queued requests) and report
+ * on `ticket`: BFP_OK (result in *out, ticket released), BFP_PENDING, or an
+ * error. Never blocks.                                                    */
+int mg_server_poll(mg_server* s, uint64_t ticket, mg_result* out);
+int mg_server_stats(const mg_server* s, int* queued, int* running, size_t* resident_bytes);
+int mg_server_destroy(mg_server* s);
+
 /* Launch-shape tuning (process-wide; results do not depend on it):
  * "star2d_rows" / "star3d_rows" = rows or planes one wave of the star
  * stencil kernels marches on large grids, "star2d_small_n" /

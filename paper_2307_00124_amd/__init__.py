@@ -387,6 +387,57 @@ class Batch:
         return b.value, n.value
 
 
+class Server:
+    """A request server in a torch-allocated arena of `budget` bytes
+    (mg_server_* calls). submit() returns a ticket; poll() never blocks."""
+
+    def __init__(self, budget: int, max_slots: int = 8, max_queue: int = 1 << 20,
+                 device="cuda"):
+        self.arena = torch.empty(budget + 256, dtype=torch.uint8, device=device)
+        off = (-self.arena.data_ptr()) % 256
+        self.arena = self.arena[off:off + budget]
+        cfg = abi.mg_server_cfg(max_slots, max_queue)
+        s = C.c_void_p()
+        check(lib.mg_server_create(C.byref(cfg), _ptr(self.arena), budget, C.byref(s)),
+              "mg_server_create")
+        self.s = s
+
+    def __del__(self):
+        s = getattr(self, "s", None)
+        if s is not None and s.value:
+            lib.mg_server_destroy(s)
+            self.s = None
+
+    def submit(self, params: abi.mg_params, rhs: list, x_out: torch.Tensor) -> int:
+        """rhs[j - 1]: contiguous FP64 device tensor of f on level j (kept
+        alive by the caller until the request is done); x_out: FP64 device
+        tensor of (2^L + 1)^ndim values."""
+        req = abi.mg_request()
+        req.prm = params
+        for j, f in enumerate(rhs):
+            if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous():
+                raise ValueError("rhs entries must be contiguous float64 device tensors")
+            req.rhs_dev[j] = f.data_ptr()
+        req.x_out_dev = x_out.data_ptr()
+        t = C.c_uint64()
+        check(lib.mg_server_submit(self.s, C.byref(req), C.byref(t)), "mg_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (status, gpu_ms)."""
+        r = abi.mg_result()
+        rc = lib.mg_server_poll(self.s, ticket, C.byref(r))
+        if rc == abi.BFP_PENDING:
+            return None
+        check(rc, "mg_server_poll")
+        return r.status, r.gpu_ms
+
+    def stats(self) -> tuple[int, int, int]:
+        q, r, b = C.c_int(), C.c_int(), C.c_size_t()
+        check(lib.mg_server_stats(self.s, C.byref(q), C.byref(r), C.byref(b)), "mg_server_stats")
+        return q.value, r.value, b.value
+
+
 def mg_params_init(ndim: int, L: int, w: int, progressive: bool = True, nu1: int = 1,
                    nu2: int = 0, N: int = 2, policy: int = MG_POLICY_NN_IR_FIRST_Q,
                    eta_percent: int = 23, min_storage_bits: int = 0) -> abi.mg_params:

@@ -54,6 +54,19 @@ class mg_params(C.Structure):
                 ("c1", bfp_scalar), ("c2", bfp_scalar), ("c1_gamma", bfp_scalar)]
 
 
+class mg_server_cfg(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32)]
+
+
+class mg_request(C.Structure):
+    _fields_ = [("prm", mg_params), ("rhs_dev", C.c_void_p * MG_MAX_LEVELS),
+                ("x_out_dev", C.c_void_p)]
+
+
+class mg_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("gpu_ms", C.c_float)]
+
+
 P = C.POINTER
 VP = C.c_void_p
 I = C.c_int
@@ -96,6 +109,11 @@ SIGNATURES = {
     "mg_solve_batch": (I, [VP, VP, VP]),
     "mg_batch_get_vec": (I, [VP, I, I, I, P(bfp_vec)]),
     "mg_batch_counters": (I, [VP, P(C.c_double), P(I64)]),
+    "mg_server_create": (I, [P(mg_server_cfg), VP, C.c_size_t, P(VP)]),
+    "mg_server_submit": (I, [VP, P(mg_request), P(C.c_uint64)]),
+    "mg_server_poll": (I, [VP, C.c_uint64, P(mg_result)]),
+    "mg_server_stats": (I, [VP, P(I), P(I), P(C.c_size_t)]),
+    "mg_server_destroy": (I, [VP]),
     "bfp_tuning_set": (I, [C.c_char_p, I]),
     "bfp_last_error": (C.c_char_p, []),
 }

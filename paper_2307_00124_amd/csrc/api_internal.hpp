@@ -40,4 +40,7 @@ int exec_max_points();
 // the program's table of distinct blocks (filled into `metas`).
 int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas);
 
+// validation of multigrid parameters (BFP_OK or the error of mg_params checks)
+int params_ok(const mg_params* p);
+
 }  // namespace bfpk

@@ -874,3 +874,5 @@ int mg_batch_counters(const mg_batch* b, double* bytes, int64_t* launches) {
 
 }  // extern "C"
 static_assert(bfpk::kMaxLevels == MG_MAX_LEVELS, "right-hand-side table rows");
+
+int bfpk::params_ok(const mg_params* p) { return check_params(p); }

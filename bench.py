@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--loop-sample", type=int, default=32,
                     help="problems solved one at a time for the batched comparison")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--serve", type=int, default=2000,
+                    help="requests of the serving trace (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--only", choices=["all", "kernel", "copy"], default="all",
                     help="kernel: only the dominant-kernel loop (for profiler runs); copy: only "
                          "a plain 1 GiB device copy (counter calibration)")
@@ -226,6 +229,11 @@ def main():
     if args.batch > 0:
         batch = bench_batch(args, P, W, np, torch, dev, stream, ev)
 
+    # ---------------------------------------------------------- serving ---
+    serving = None
+    if args.serve > 0:
+        serving = bench_serve(args, P, W, np, torch, dev)
+
     # ---------------------------------------------------- CPU baseline ----
     cpu = None
     if not args.no_cpu:
@@ -283,6 +291,7 @@ def main():
         "stencil_apply": stencils,
         "sweep": sweep,
         "batched": batch,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -370,6 +379,95 @@ def bench_batch(args, P, W, np, torch, dev, stream, ev):
             "worst_err_over_disc_sampled": round(worst, 4),
             "loop_dof_per_s": loop_rate, "loop_sample": len(sample),
             "speedup_vs_loop": round(rate / loop_rate, 2)}
+
+
+def sine_f_dev(torch, j, modes, ndim, dev):
+    """The workload's sine-mode right-hand side on the padded level-j grid,
+    evaluated on the device (input generation only)."""
+    side = (1 << j) + 1
+    x = torch.arange(side, dtype=torch.float64, device=dev) * (2.0 ** -j)
+    f = torch.zeros((side,) * ndim, dtype=torch.float64, device=dev)
+    for i in range(modes.k.shape[0]):
+        parts = []
+        for d in range(ndim):
+            s = torch.sin(math.pi * float(modes.k[i, d]) * x)
+            s[0] = 0.0
+            s[-1] = 0.0
+            parts.append(s)
+        t = parts[0]
+        for v in parts[1:]:
+            t = torch.multiply(v.reshape((-1,) + (1,) * t.dim()), t)
+        f += float(modes.a[i]) * t
+    return f
+
+
+def bench_serve(args, P, W, np, torch, dev):
+    """The serving workload: open-loop Poisson arrivals (2000 req/s) of mixed
+    2D/3D solves of mixed sizes and widths, run by the request server with
+    several slots, against the same trace through a one-slot server (solves
+    one after the other)."""
+    trace = W.serving_trace(args.serve, rate=2000.0, seed=2)
+    prms, rhs, outs, dofs = [], [], [], []
+    for r in trace:
+        L = r.level
+        prms.append(P.batch_params(r.ndim, L, r.w))
+        rhs.append([sine_f_dev(torch, j, r.modes, r.ndim, dev) for j in range(1, L + 1)])
+        outs.append(torch.zeros(((1 << L) + 1,) * r.ndim, dtype=torch.float64, device=dev))
+        dofs.append(((1 << L) - 1) ** r.ndim)
+    torch.cuda.synchronize()
+
+    def run(slots, count):
+        S = P.Server(48 << 30, max_slots=slots)
+        # warm-up: one resident hierarchy per parameter set and slot
+        seen = {}
+        for i in range(count):
+            key = (trace[i].ndim, trace[i].level, trace[i].w)
+            seen.setdefault(key, i)
+        warm = {S.submit(prms[i], rhs[i], outs[i]) for i in seen.values() for _ in range(slots)}
+        while warm:
+            for t, st, _ in S.collect():
+                warm.discard(t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nxt, pending, lat, done_at = 0, {}, [], []
+        while nxt < count or pending:
+            now = time.perf_counter() - t0
+            while nxt < count and trace[nxt].t_arrival <= now:
+                pending[S.submit(prms[nxt], rhs[nxt], outs[nxt])] = nxt
+                nxt += 1
+            for t, st, _ in S.collect():
+                i = pending.pop(t)
+                fin = time.perf_counter() - t0
+                lat.append(fin - trace[i].t_arrival)
+                done_at.append(fin)
+        span = max(done_at) - trace[0].t_arrival
+        lat_ms = np.asarray(lat) * 1e3
+        return {"requests": count, "slots": slots,
+                "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                "dof_per_s": sum(dofs[:count]) / span, "span_s": round(span, 3)}
+
+    served = run(args.serve_slots, len(trace))
+    seq = run(1, min(len(trace), 500))
+    offered = sum(dofs) / trace[-1].t_arrival
+    # alone vs in the mix: re-solve a few requests one at a time
+    same = True
+    mix = [outs[i].clone() for i in range(8)]
+    S1 = P.Server(8 << 30, max_slots=1)
+    for i in range(8):
+        outs[i].zero_()
+        t = S1.submit(prms[i], rhs[i], outs[i])
+        while S1.poll(t) is None:
+            pass
+    torch.cuda.synchronize()
+    for i in range(8):
+        same = same and bool(torch.equal(outs[i], mix[i]))
+    return {"workload": f"{len(trace)} requests, Poisson arrivals at 2000/s (seed 2), 50% 2D "
+                        "sides 65..1025, 50% 3D sides 33..129, w in {8,16,24,32}, FMG with "
+                        "N=max(2,L-3) IR-V(1,0)", "offered_dof_per_s": offered,
+            "server": served, "sequential_one_slot": seq,
+            "speedup_dof_per_s": round(served["dof_per_s"] / seq["dof_per_s"], 2),
+            "alone_equals_mix": same}
 
 
 if __name__ == "__main__":

@@ -351,7 +351,9 @@ int mg_batch_counters(const mg_batch* b, double* bytes, int64_t* launches);
  * waits while neither a slot nor memory is free (admission in arrival
  * order). A slot runs the whole solve: mg_set_rhs on every level, mg_fmg,
  * and the finest iterate converted to FP64 into x_out_dev. Results are
- * bit-identical to the same solve run alone. Hierarchy creation on first
+ * bit-identical to the same solve run alone. The slots' streams do not wait
+ * on any other stream: a request's buffers must be ready (the work that
+ * fills them finished) when it is submitted. Hierarchy creation on first
  * use of a parameter set synchronizes that slot's stream. Not thread-safe:
  * one host thread drives a server.                                       */
 typedef struct mg_server mg_server;
@@ -378,6 +380,10 @@ int mg_server_submit(mg_server* s, const mg_request* req, uint64_t* ticket);
  * on `ticket`: BFP_OK (result in *out, ticket released), BFP_PENDING, or an
  * error. Never blocks.                                                    */
 int mg_server_poll(mg_server* s, uint64_t ticket, mg_result* out);
+/* Make progress and hand over up to `cap` finished requests (tickets and
+ * results, in no particular order; their tickets are released); *count is
+ * the number handed over. Never blocks.                                   */
+int mg_server_collect(mg_server* s, uint64_t* tickets, mg_result* results, int cap, int* count);
 int mg_server_stats(const mg_server* s, int* queued, int* running, size_t* resident_bytes);
 int mg_server_destroy(mg_server* s);
 

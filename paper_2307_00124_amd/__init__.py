@@ -432,6 +432,16 @@ class Server:
         check(rc, "mg_server_poll")
         return r.status, r.gpu_ms
 
+    def collect(self, cap: int = 256) -> list:
+        """Finished requests since the last call: [(ticket, status, gpu_ms)]."""
+        if not hasattr(self, "_ct") or len(self._ct) < cap:
+            self._ct = (C.c_uint64 * cap)()
+            self._cr = (abi.mg_result * cap)()
+        n = C.c_int()
+        check(lib.mg_server_collect(self.s, self._ct, self._cr, cap, C.byref(n)),
+              "mg_server_collect")
+        return [(self._ct[i], self._cr[i].status, self._cr[i].gpu_ms) for i in range(n.value)]
+
     def stats(self) -> tuple[int, int, int]:
         q, r, b = C.c_int(), C.c_int(), C.c_size_t()
         check(lib.mg_server_stats(self.s, C.byref(q), C.byref(r), C.byref(b)), "mg_server_stats")

@@ -113,6 +113,7 @@ SIGNATURES = {
     "mg_server_submit": (I, [VP, P(mg_request), P(C.c_uint64)]),
     "mg_server_poll": (I, [VP, C.c_uint64, P(mg_result)]),
     "mg_server_stats": (I, [VP, P(I), P(I), P(C.c_size_t)]),
+    "mg_server_collect": (I, [VP, P(C.c_uint64), P(mg_result), I, P(I)]),
     "mg_server_destroy": (I, [VP]),
     "bfp_tuning_set": (I, [C.c_char_p, I]),
     "bfp_last_error": (C.c_char_p, []),

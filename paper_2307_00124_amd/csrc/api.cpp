@@ -415,6 +415,50 @@ int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta
 
 }  // namespace bfpk
 
+namespace bfpk {
+
+int from_f64_impl(const double* src_dev, const double* const* table_dev, int index,
+                  int64_t log2_scale, bfp_vec* dst, hipStream_t s) {
+  int rc = check_vec(dst, "dst");
+  if (rc) return rc;
+  if (!src_dev && !table_dev) return fail(BFP_EINVAL, "src is NULL");
+  if (log2_scale < -(1ll << 30) || log2_scale > (1ll << 30)) return fail(BFP_EINVAL, "log2_scale out of range");
+  ConvertLaunch L{};
+  L.src = src_dev;
+  L.src_table = table_dev;
+  L.table_index = index;
+  L.mant = dst->mant;
+  L.meta = dst->meta;
+  L.ndim = dst->ndim;
+  L.n = dst->n;
+  L.pitch = dst->pitch;
+  L.bits = dst->storage_bits;
+  L.w = dst->w;
+  L.log2_scale = log2_scale;
+  return hip_check(launch_from_f64(L, s), "bfp_vec_from_f64");
+}
+
+int to_f64_impl(const bfp_vec* src, double* dst_dev, double* const* table_dev, int index,
+                hipStream_t s) {
+  int rc = check_vec(src, "src");
+  if (rc) return rc;
+  if (!dst_dev && !table_dev) return fail(BFP_EINVAL, "dst is NULL");
+  ConvertLaunch L{};
+  L.dst = dst_dev;
+  L.dst_table = table_dev;
+  L.table_index = index;
+  L.mant = src->mant;
+  L.meta = src->meta;
+  L.ndim = src->ndim;
+  L.n = src->n;
+  L.pitch = src->pitch;
+  L.bits = src->storage_bits;
+  L.w = src->w;
+  return hip_check(launch_to_f64(L, s), "bfp_vec_to_f64");
+}
+
+}  // namespace bfpk
+
 using namespace bfpk;
 
 extern "C" {
@@ -454,37 +498,13 @@ int bfp_meta_reset(int64_t* meta_dev, void* stream) {
 }
 
 int bfp_vec_from_f64(const double* src_dev, int64_t log2_scale, bfp_vec* dst, void* stream) {
-  int rc = check_vec(dst, "dst");
-  if (rc) return rc;
   if (!src_dev) return fail(BFP_EINVAL, "src is NULL");
-  if (log2_scale < -(1ll << 30) || log2_scale > (1ll << 30)) return fail(BFP_EINVAL, "log2_scale out of range");
-  ConvertLaunch L{};
-  L.src = src_dev;
-  L.mant = dst->mant;
-  L.meta = dst->meta;
-  L.ndim = dst->ndim;
-  L.n = dst->n;
-  L.pitch = dst->pitch;
-  L.bits = dst->storage_bits;
-  L.w = dst->w;
-  L.log2_scale = log2_scale;
-  return hip_check(launch_from_f64(L, (hipStream_t)stream), "bfp_vec_from_f64");
+  return from_f64_impl(src_dev, nullptr, 0, log2_scale, dst, (hipStream_t)stream);
 }
 
 int bfp_vec_to_f64(const bfp_vec* src, double* dst_dev, void* stream) {
-  int rc = check_vec(src, "src");
-  if (rc) return rc;
   if (!dst_dev) return fail(BFP_EINVAL, "dst is NULL");
-  ConvertLaunch L{};
-  L.dst = dst_dev;
-  L.mant = src->mant;
-  L.meta = src->meta;
-  L.ndim = src->ndim;
-  L.n = src->n;
-  L.pitch = src->pitch;
-  L.bits = src->storage_bits;
-  L.w = src->w;
-  return hip_check(launch_to_f64(L, (hipStream_t)stream), "bfp_vec_to_f64");
+  return to_f64_impl(src, dst_dev, nullptr, 0, (hipStream_t)stream);
 }
 
 int bfp_vec_check(const bfp_vec* v, void* stream) {

@@ -40,6 +40,16 @@ int exec_max_points();
 // the program's table of distinct blocks (filled into `metas`).
 int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas);
 
+// FP64 <-> BFP with the FP64 pointer given directly, or (pointer null) read
+// on the device from table[index]
+int from_f64_impl(const double* src_dev, const double* const* table_dev, int index,
+                  int64_t log2_scale, bfp_vec* dst, hipStream_t s);
+int to_f64_impl(const bfp_vec* src, double* dst_dev, double* const* table_dev, int index,
+                hipStream_t s);
+// mg_set_rhs with the level's FP64 right-hand side read from table[index]
+int set_rhs_table(mg_hierarchy* h, int level, const double* const* table_dev, int index,
+                  hipStream_t s);
+
 // validation of multigrid parameters (BFP_OK or the error of mg_params checks)
 int params_ok(const mg_params* p);
 

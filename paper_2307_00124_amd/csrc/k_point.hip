@@ -93,6 +93,7 @@ __device__ __forceinline__ bool f64_parts(double x, int64_t& z, int64_t& e, bool
 
 // pass 1: max_i nu(x_i) over the interior, and the non-finite flag
 __global__ __launch_bounds__(kBlock) void k_f64_nu(const ConvertLaunch L) {
+  const double* src = L.src ? L.src : L.src_table[L.table_index];
   const int64_t n = L.n, side = n + 2;
   const int64_t nchunk = (side + 1023) / 1024;
   const int64_t items = row_items(n, L.ndim);
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_f64_nu(const ConvertLaunch L) {
       if (c < 1 || c > n) continue;
       int64_t z, e;
       bool fin;
-      if (f64_parts(L.src[rr * side + c], z, e, fin)) {
+      if (f64_parts(src[rr * side + c], z, e, fin)) {
         const int64_t nu = msb64(z) + e;
         best = nu > best ? nu : best;
       }
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_f64_nu(const ConvertLaunch L) {
 // pass 2: m_i = floor(x_i / 2^(max nu - w)), exponent max nu - w + log2_scale
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_f64_conv(const ConvertLaunch L) {
+  const double* src = L.src ? L.src : L.src_table[L.table_index];
   const int64_t n = L.n, side = n + 2;
   const int64_t nchunk = (side + 1023) / 1024;
   const int64_t items = row_items(n, L.ndim);
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_f64_conv(const ConvertLaunch L) {
       if (c < 1 || c > n) continue;
       int64_t z, e;
       bool fin;
-      if (f64_parts(L.src[rr * side + c], z, e, fin)) {
+      if (f64_parts(src[rr * side + c], z, e, fin)) {
         const int64_t sh = e - eq;
         out[k] = sh >= 0 ? (int64_t)((uint64_t)z << sh) : shr_floor(z, -sh);
         tmax = out[k] > tmax ? out[k] : tmax;
@@ -180,6 +182,7 @@ hipError_t launch_from_f64(const ConvertLaunch& L, hipStream_t s) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_to_f64(const ConvertLaunch L) {
+  double* dst = L.dst ? L.dst : L.dst_table[L.table_index];
   const int64_t side = L.n + 2;
   const int64_t nchunk = (side + 1023) / 1024;
   const int64_t row = blockIdx.x / nchunk;                 // every row, ring included
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_to_f64(const ConvertLaunch L) {
   const T* M = static_cast<const T*>(L.mant);
   for (int k = 0; k < 4; ++k) {
     const int64_t c = c0 + k;
-    if (c < side) L.dst[row * side + c] = ldexp((double)M[row * L.pitch + c], e);
+    if (c < side) dst[row * side + c] = ldexp((double)M[row * L.pitch + c], e);
   }
 }
 

@@ -64,6 +64,12 @@ hipError_t launch_point(const PointLaunch& L, hipStream_t s);
 struct ConvertLaunch {
   const double* src;   // dense (n+2)^ndim
   double* dst;
+  // when src (from_f64) or dst (to_f64) is null, the FP64 pointer is read
+  // on the device from table[index] (lets a captured graph serve requests
+  // whose buffers change)
+  const double* const* src_table;
+  double* const* dst_table;
+  int table_index;
   void* mant;
   int64_t* meta;
   int ndim;

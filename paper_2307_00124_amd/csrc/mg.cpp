@@ -876,3 +876,10 @@ int mg_batch_counters(const mg_batch* b, double* bytes, int64_t* launches) {
 static_assert(bfpk::kMaxLevels == MG_MAX_LEVELS, "right-hand-side table rows");
 
 int bfpk::params_ok(const mg_params* p) { return check_params(p); }
+
+int bfpk::set_rhs_table(mg_hierarchy* h, int level, const double* const* table_dev, int index,
+                        hipStream_t s) {
+  if (!h || level < 1 || level > h->prm.L) return fail(BFP_EINVAL, "bad level");
+  const int64_t shift = h->prm.ndim == 2 ? -2 * level - 2 : -2 * level - 3;
+  return from_f64_impl(nullptr, table_dev, index, shift, &h->lv[level].b, s);
+}

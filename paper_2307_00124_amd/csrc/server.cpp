@@ -6,8 +6,12 @@
 // the budget allows, idle ones evicted least-recently-used when it does not)
 // and one of `max_slots` execution slots, each a HIP stream of its own. A
 // slot runs the request's whole solve — FP64 right-hand sides of every level
-// to BFP, FMG, the finest iterate back to FP64 into the caller's buffer — and
-// records an event; polling checks events without blocking, frees finished
+// to BFP, FMG, the finest iterate back to FP64 into the caller's buffer — as
+// one replay of a HIP graph captured once per resident hierarchy (the
+// request's buffers reach the graph through a small device table of
+// pointers, copied in before the replay), so a request costs the host two
+// calls instead of a hundred launches; it then records an event. Polling
+// checks events without blocking, frees finished
 // slots and admits queued requests in arrival order (continuous batching:
 // requests join as slots and memory free up, and the work of all running
 // slots overlaps on the device). Each result is the same, bit for bit, as
@@ -33,6 +37,8 @@ struct Resident {
   mg_params prm;
   mg_hierarchy* h = nullptr;
   size_t off = 0, size = 0;
+  const double** table = nullptr;   // device: rhs[0..L-1], x_out
+  hipGraphExec_t graph = nullptr;
   bool busy = false;
   uint64_t last_use = 0;
 };
@@ -40,10 +46,20 @@ struct Resident {
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t start = nullptr, done = nullptr;
+  const double** staging = nullptr;   // pinned host copy of a request's table
   int res = -1;
   uint64_t ticket = 0;
   bool busy = false;
 };
+
+constexpr size_t kTableBytes = 256;   // MG_MAX_LEVELS + 1 pointers, rounded up
+
+void drop(Resident& r) {
+  if (r.graph) hipGraphExecDestroy(r.graph);
+  r.graph = nullptr;
+  mg_hierarchy_destroy(r.h);
+  r.h = nullptr;
+}
 
 struct Queued {
   uint64_t ticket;
@@ -72,8 +88,28 @@ struct mg_server {
       if (s.start) hipEventDestroy(s.start);
       if (s.done) hipEventDestroy(s.done);
       if (s.stream) hipStreamDestroy(s.stream);
+      if (s.staging) hipHostFree(s.staging);
     }
-    for (Resident& r : pool) mg_hierarchy_destroy(r.h);
+    for (Resident& r : pool) drop(r);
+  }
+
+  // capture the whole solve of a resident hierarchy, reading the request's
+  // buffers from its table
+  int capture(Resident& r, hipStream_t s) {
+    hipGraph_t g = nullptr;
+    int rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
+    if (rc) return rc;
+    const int L = r.prm.L;
+    for (int j = 1; j <= L && !rc; ++j) rc = set_rhs_table(r.h, j, r.table, j - 1, s);
+    if (!rc) rc = mg_fmg(r.h, s);
+    bfp_vec x;
+    if (!rc) rc = mg_get_vec(r.h, L, 0, &x);
+    if (!rc) rc = to_f64_impl(&x, nullptr, (double* const*)r.table, L, s);
+    const int rc_end = hip_check(hipStreamEndCapture(s, &g), "graph capture");
+    if (!rc) rc = rc_end;
+    if (!rc) rc = hip_check(hipGraphInstantiate(&r.graph, g, nullptr, nullptr, 0), "graph instantiate");
+    if (g) hipGraphDestroy(g);
+    return rc;
   }
 
   // first-fit allocation of `size` bytes of the arena; false when no range fits
@@ -110,8 +146,9 @@ struct mg_server {
     *rc = BFP_OK;
     for (size_t i = 0; i < pool.size(); ++i)
       if (!pool[i].busy && !std::memcmp(&pool[i].prm, &p, sizeof p)) return (int)i;
-    const size_t need = align256(mg_hierarchy_bytes(&p));
-    if (need == 0 || need > bytes) {
+    const size_t hb = align256(mg_hierarchy_bytes(&p));
+    const size_t need = hb + kTableBytes;
+    if (hb == 0 || need > bytes) {
       *rc = fail(BFP_ENOMEM, "a request needs %zu bytes of the %zu-byte arena", need, bytes);
       return -1;
     }
@@ -122,7 +159,7 @@ struct mg_server {
         if (!pool[i].busy && (victim < 0 || pool[i].last_use < pool[victim].last_use))
           victim = (int)i;
       if (victim < 0) return -1;   // everything resident is running: wait
-      mg_hierarchy_destroy(pool[victim].h);
+      drop(pool[victim]);
       release(pool[victim].off, pool[victim].size);
       pool.erase(pool.begin() + victim);
       for (Slot& sl : slots)
@@ -132,7 +169,9 @@ struct mg_server {
     r.prm = p;
     r.off = off;
     r.size = need;
-    if ((*rc = mg_hierarchy_create(&p, arena + off, need, s, &r.h))) {
+    r.table = (const double**)(arena + off + hb);
+    if ((*rc = mg_hierarchy_create(&p, arena + off, hb, s, &r.h)) || (*rc = capture(r, s))) {
+      if (r.h) drop(r);
       release(off, need);
       return -1;
     }
@@ -142,14 +181,14 @@ struct mg_server {
 
   int launch(Slot& sl, int res, const Queued& q) {
     Resident& R = pool[res];
-    mg_hierarchy* h = R.h;
-    const mg_params& p = R.prm;
-    int rc = hip_check(hipEventRecord(sl.start, sl.stream), "request start event");
-    for (int j = 1; j <= p.L && !rc; ++j) rc = mg_set_rhs(h, j, q.req.rhs_dev[j - 1], sl.stream);
-    if (!rc) rc = mg_fmg(h, sl.stream);
-    bfp_vec x;
-    if (!rc) rc = mg_get_vec(h, p.L, 0, &x);
-    if (!rc) rc = bfp_vec_to_f64(&x, q.req.x_out_dev, sl.stream);
+    const int L = R.prm.L;
+    // the slot is idle, so its staging copy of the previous table was consumed
+    for (int j = 0; j < L; ++j) sl.staging[j] = q.req.rhs_dev[j];
+    sl.staging[L] = q.req.x_out_dev;
+    int rc = hip_check(hipMemcpyAsync(R.table, sl.staging, (L + 1) * sizeof(double*),
+                                      hipMemcpyHostToDevice, sl.stream), "request table");
+    if (!rc) rc = hip_check(hipEventRecord(sl.start, sl.stream), "request start event");
+    if (!rc) rc = hip_check(hipGraphLaunch(R.graph, sl.stream), "request graph");
     if (!rc) rc = hip_check(hipEventRecord(sl.done, sl.stream), "request done event");
     if (rc) return rc;
     R.busy = true;
@@ -219,6 +258,8 @@ int mg_server_create(const mg_server_cfg* cfg, void* arena_dev, size_t bytes, mg
     int rc = hip_check(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking), "slot stream");
     if (!rc) rc = hip_check(hipEventCreate(&sl.start), "slot event");
     if (!rc) rc = hip_check(hipEventCreate(&sl.done), "slot event");
+    if (!rc) rc = hip_check(hipHostMalloc((void**)&sl.staging, kTableBytes, hipHostMallocDefault),
+                            "slot staging");
     if (rc) { delete s; return rc; }
   }
   *out = s;
@@ -255,6 +296,21 @@ int mg_server_poll(mg_server* s, uint64_t ticket, mg_result* out) {
   for (const Queued& q : s->queue)
     if (q.ticket == ticket) return BFP_PENDING;
   return fail(BFP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+}
+
+int mg_server_collect(mg_server* s, uint64_t* tickets, mg_result* results, int cap, int* count) {
+  if (!s || !count || (cap > 0 && (!tickets || !results))) return fail(BFP_EINVAL, "NULL argument");
+  int rc = s->progress();
+  if (rc) return rc;
+  int k = 0;
+  for (auto it = s->finished.begin(); it != s->finished.end() && k < cap;) {
+    tickets[k] = it->first;
+    results[k] = it->second;
+    ++k;
+    it = s->finished.erase(it);
+  }
+  *count = k;
+  return BFP_OK;
 }
 
 int mg_server_stats(const mg_server* s, int* queued, int* running, size_t* resident_bytes) {

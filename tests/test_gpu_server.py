@@ -44,6 +44,7 @@ def alone(prm, rhs):
 
 
 def run_server(S, items):
+    torch.cuda.synchronize()   # inputs ready before the server's streams read them
     tickets = [S.submit(prm, rhs, x) for prm, rhs, x in items]
     pending = dict(enumerate(tickets))
     for _ in range(2_000_000):
@@ -84,3 +85,22 @@ def test_server_errors():
     assert e.value.code == P.abi.BFP_ENOMEM
     with pytest.raises(P.BFPError):
         S.poll(12345)
+
+
+def test_graph_replays_match_eager_with_eager_work_between():
+    """A resident hierarchy's captured solve replayed several times, with
+    eager library work and synchronizations in between, matches the eager
+    solve every time."""
+    reqs = requests(3, seed=4)
+    items = [make(r) for r in reqs]
+    refs = [alone(prm, rhs) for prm, rhs, _ in items]
+    S = P.Server(256 << 20, max_slots=1)
+    for rep in range(4):
+        for k, (prm, rhs, x) in enumerate(items):
+            x.zero_()
+            torch.cuda.synchronize()   # the server's streams do not wait on torch's
+            run_server(S, [(prm, rhs, x)])
+            assert torch.equal(x, refs[k]), (rep, k)
+            # eager work between replays: a solve of another request
+            assert torch.equal(alone(*items[(k + 1) % 3][:2]), refs[(k + 1) % 3])
+            torch.cuda.synchronize()

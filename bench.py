@@ -181,6 +181,9 @@ def main():
     step_bytes = bytes_after - bytes_before
     step_launches = launches_after - launches_before
 
+    # ------------------------------------- FP64 multigrid comparator ---
+    fp64 = bench_fp64(P, torch, f, L, us, h2, disc, stream, ev)
+
     # --------------------------------------- plain stencil applies ------
     # z = A x (two int32 streams), 2D 4095^2 and 3D 511^3
     stencils = {}
@@ -288,6 +291,8 @@ def main():
                      "kernel": "k_star2d (5-point residual A x - b, int32, finest level)",
                      "avg_us": round(kern_us, 2), "bytes_per_launch": kern_bytes},
         "solve_algorithmic_gbs": step_bytes / (ms * 1e-3) / 1e9,
+        "fp64_mg_comparator": fp64,
+        "bfp_over_fp64_dof_per_s": round((dof / (ms * 1e-3)) / fp64["dof_per_s"], 2),
         "stencil_apply": stencils,
         "sweep": sweep,
         "batched": batch,
@@ -379,6 +384,74 @@ def bench_batch(args, P, W, np, torch, dev, stream, ev):
             "worst_err_over_disc_sampled": round(worst, 4),
             "loop_dof_per_s": loop_rate, "loop_sample": len(sample),
             "speedup_vs_loop": round(rate / loop_rate, 2)}
+
+
+def bench_fp64(P, torch, f, L, us, h2, disc, stream, ev):
+    """FP64 multigrid on the same GPU with the same schedule (FMG, N = 2
+    IR-V(1,0), the same Chebyshev coefficients, the scaled operators
+    A' = [1; -1/4], R' = P^T, bilinear P), written with plain torch tensor
+    ops: the floating-point comparator of the metric."""
+    prm = P.mg_params_init(2, L, 32, True, 1, 0, 2, P.MG_POLICY_NN_IR_FIRST_Q, 23)
+    c1 = prm.c1.m * 2.0 ** prm.c1.exp
+    c2 = prm.c2.m * 2.0 ** prm.c2.exp
+    b = [None] + [f[j] * (2.0 ** (-2 * j) / 4.0) for j in range(1, L + 1)]
+
+    def A(x):
+        y = torch.zeros_like(x)
+        y[1:-1, 1:-1] = x[1:-1, 1:-1] - 0.25 * (x[:-2, 1:-1] + x[2:, 1:-1] + x[1:-1, :-2] + x[1:-1, 2:])
+        return y
+
+    def R(x):                        # fine (2n+1) -> coarse n, weights 2^-2 (4,2,1)
+        nc = (x.shape[0] - 3) // 2
+        c = torch.zeros((nc + 2, nc + 2), dtype=x.dtype, device=x.device)
+        e = slice(2, 2 * nc + 1, 2)
+        m = slice(1, 2 * nc, 2)
+        p_ = slice(3, 2 * nc + 2, 2)
+        c[1:-1, 1:-1] = (x[e, e] + 0.5 * (x[m, e] + x[p_, e] + x[e, m] + x[e, p_]) +
+                         0.25 * (x[m, m] + x[m, p_] + x[p_, m] + x[p_, p_]))
+        return c
+
+    def Pr(c):                       # coarse n -> fine 2n+1, bilinear
+        nc = c.shape[0] - 2
+        x = torch.zeros((2 * nc + 3, 2 * nc + 3), dtype=c.dtype, device=c.device)
+        x[0::2, 0::2] = c
+        x[1::2, 0::2] = 0.5 * (c[:-1, :] + c[1:, :])
+        x[:, 1::2] = 0.5 * (x[:, 0:-1:2] + x[:, 2::2])
+        x[0, :] = 0
+        x[-1, :] = 0
+        x[:, 0] = 0
+        x[:, -1] = 0
+        return x
+
+    def V(l, r):
+        y = c2 * A(r) + c1 * r
+        if l > 1:
+            d = V(l - 1, R(A(y) - r))
+            y = y - Pr(d)
+        return y
+
+    def fmg():
+        x = torch.zeros((3, 3), dtype=torch.float64, device=f[1].device)
+        for l in range(1, L + 1):
+            if l > 1:
+                x = Pr(x)
+            for _ in range(2):
+                x = x - V(l, A(x) - b[l])
+        return x
+
+    fmg()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    x = fmg()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    err = math.sqrt(float(((x - us)[1:-1, 1:-1] ** 2).sum()) * h2)
+    dof = ((1 << L) - 1) ** 2
+    return {"what": "FP64 FMG, same schedule and coefficients, torch tensor ops on the same GPU",
+            "ms": round(ms, 3), "dof_per_s": dof / (ms * 1e-3),
+            "err_over_disc": round(err / disc, 4)}
 
 
 def sine_f_dev(torch, j, modes, ndim, dev):

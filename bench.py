@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--loop-sample", type=int, default=32,
                     help="problems solved one at a time for the batched comparison")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--level3d", type=int, default=9, help="3D solve level (0: skip)")
     ap.add_argument("--serve", type=int, default=2000,
                     help="requests of the serving trace (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -215,6 +216,11 @@ def main():
         del x3, z3
         torch.cuda.empty_cache()
 
+    # ------------------------------------------------------- 3D solve ---
+    solve3d = None
+    if args.level3d > 0:
+        solve3d = bench_3d(args, P, W, torch, dev, stream, ev)
+
     # ------------------------------------------------------ width sweep ---
     sweep = []
     for w in [int(s) for s in args.sweep.split(",") if s]:
@@ -294,6 +300,7 @@ def main():
         "fp64_mg_comparator": fp64,
         "bfp_over_fp64_dof_per_s": round((dof / (ms * 1e-3)) / fp64["dof_per_s"], 2),
         "stencil_apply": stencils,
+        "solve_3d": solve3d,
         "sweep": sweep,
         "batched": batch,
         "serving": serving,
@@ -452,6 +459,59 @@ def bench_fp64(P, torch, f, L, us, h2, disc, stream, ev):
     return {"what": "FP64 FMG, same schedule and coefficients, torch tensor ops on the same GPU",
             "ms": round(ms, 3), "dof_per_s": dof / (ms * 1e-3),
             "err_over_disc": round(err / disc, 4)}
+
+
+def bench_3d(args, P, W, torch, dev, stream, ev):
+    """3D Poisson, 7-point, (2^L + 1)^3 grid: IR-V(2,2) from zero with
+    progressive widths (finest inner 24, working 2L + 8), qcomp for IR
+    residuals, nnqcomp elsewhere, until the error reaches 1.1x the
+    discretization error; then the same number of iterations timed."""
+    L = args.level3d
+    n = (1 << L) - 1
+    p = P.mg_params_init(3, L, 24, True, 2, 2, 2, P.MG_POLICY_NN_IR_Q, 13)
+    p.min_storage_bits = 32
+    H = P.Hierarchy(p)
+    f = torch.from_numpy(W.manufactured_f(L, 3)).to(dev)
+    us = torch.from_numpy(W.manufactured_u(L, 3)).to(dev)
+    h = 2.0 ** -L
+    kappa = (math.pi * h) ** 2 / (4.0 * math.sin(math.pi * h / 2.0) ** 2)
+    inner = (slice(1, -1),) * 3
+    norm_us = math.sqrt(float((us[inner] ** 2).sum()) * h ** 3)
+    disc = (kappa - 1.0) * norm_us
+    x0 = torch.zeros_like(f)
+    H.set_rhs(L, f, stream)
+    H.set_x(L, x0, stream)
+    ratios = []
+    for it in range(1, 25):
+        H.ir(L, 1, stream)
+        u = P.bfp_vec_to_f64(H.get_vec(L, 0), stream=stream)
+        err = math.sqrt(float(((u - us)[inner] ** 2).sum()) * h ** 3)
+        ratios.append(round(err / disc, 4))
+        del u
+        if err <= 1.1 * disc:
+            break
+    K = len(ratios)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    H.set_rhs(L, f, stream)
+    H.set_x(L, x0, stream)
+    H.ir(L, K, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    b0, _ = H.counters()
+    H.ir(L, 1, stream)
+    torch.cuda.synchronize()
+    b1, _ = H.counters()
+    del H, f, us, x0
+    torch.cuda.empty_cache()
+    return {"workload": f"3D Poisson 7-point {(1 << L) + 1}^3, {L} levels, IR-V(2,2) from zero, "
+                        "progressive widths (inner 24, working 2L+8), int32",
+            "dof": n ** 3, "iterations": K, "err_over_disc_per_iteration": ratios,
+            "at_disc_error": ratios[-1] <= 1.1, "ms": round(ms, 3),
+            "dof_per_s": n ** 3 / (ms * 1e-3),
+            "algorithmic_gbs_per_iteration": (b1 - b0) / (ms * 1e-3 / K) / 1e9}
 
 
 def sine_f_dev(torch, j, modes, ndim, dev):

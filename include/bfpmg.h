@@ -137,7 +137,10 @@ typedef struct {
 
 /* ------------------------------------------------------------ layout --- */
 
-/* Row pitch (elements, a multiple of 16 bytes) and byte size of a block.  */
+/* Row pitch (elements, a multiple of 128 bytes: rows start on cache-line
+ * boundaries when the block is 128-byte aligned) and byte size of a block.
+ * Blocks laid out by hand need only a pitch that is a multiple of 16 bytes
+ * and holds n + 2 elements, and 16-byte aligned mantissas.               */
 int bfp_layout(int ndim, int n, int storage_bits, int64_t* pitch, size_t* bytes);
 
 /* Make v the zero block: all mantissas (ring and padding included) 0,

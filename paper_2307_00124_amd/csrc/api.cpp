@@ -24,7 +24,7 @@ static thread_local std::string g_last_error;
 // ~1-2 waves per SIMD. The default picks rows = n^2 / 2^18 (2D), clamped to
 // [1, 64] and rounded down to a power of two; the tuning keys override it.
 static int g_star2d_rows_large = 0, g_star2d_small_n = 0;
-static int g_star3d_rows_large = 16, g_star3d_small_n = 64;
+static int g_star3d_rows_large = 32, g_star3d_small_n = 64;
 
 // Coarse-level executor: programs are recorded for the levels whose grids
 // hold at most this many points (0 disables the executor).
@@ -116,9 +116,11 @@ int hip_check(hipError_t e, const char* what) {
   return fail(BFP_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// rows start on 128-byte boundaries (a block is 256-byte aligned), so a
+// wave's 1 KB column segment covers whole cache lines
 int64_t pitch_for(int64_t n, int bits) {
-  const int64_t per16 = 128 / bits;  // elements per 16 bytes
-  return ((n + 2 + per16 - 1) / per16) * per16;
+  const int64_t per128 = 1024 / bits;  // elements per 128 bytes
+  return ((n + 2 + per128 - 1) / per128) * per128;
 }
 
 int64_t rows_for(int ndim, int64_t n) { return ndim == 3 ? (n + 2) * (n + 2) : (n + 2); }
@@ -342,6 +344,10 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
     L.zbits = z->storage_bits;
     L.wide = wide;
     L.rows = rows > 0 ? rows : star_rows(x->ndim, x->n);
+    {
+      const int64_t segs = (x->n + 1 + 255) / 256;
+      L.wx = segs >= 4 ? 4 : (segs >= 2 ? 2 : 1);
+    }
     return run_modes(L, mode, [&](StarLaunch& l) { return launch_star(l, s); });
   }
   if (A->kind == BFP_STENCIL_R || A->kind == BFP_STENCIL_P) {

@@ -47,6 +47,51 @@ __device__ __forceinline__ void st4(T* base, int64_t off, const int64_t (&v)[4])
   *reinterpret_cast<Q4<T>*>(base + off) = q;
 }
 
+// Streaming variants for data touched once (the y operand, the output):
+// non-temporal hints keep it from displacing re-used lines (stencil halos)
+// in the caches. Measured on MI355X: a few percent faster for the 3D star
+// kernel, slower for the 2D one (which therefore keeps plain accesses).
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+typedef int32_t v2i32 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void ld4_nt(const T* base, int64_t off, int32_t (&v)[4], bool ok) {
+  const T* p = base + (ok ? off : 0);
+  int32_t w[4];
+  if (sizeof(T) == 4) {
+    const v4i32 q = __builtin_nontemporal_load(reinterpret_cast<const v4i32*>(p));
+    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+  } else if (sizeof(T) == 2) {
+    const v2i32 q = __builtin_nontemporal_load(reinterpret_cast<const v2i32*>(p));
+    w[0] = (int16_t)(q.x & 0xffff); w[1] = (int16_t)((uint32_t)q.x >> 16);
+    w[2] = (int16_t)(q.y & 0xffff); w[3] = (int16_t)((uint32_t)q.y >> 16);
+  } else {
+    const int q = __builtin_nontemporal_load(reinterpret_cast<const int*>(p));
+    w[0] = (int8_t)(q & 0xff); w[1] = (int8_t)((q >> 8) & 0xff);
+    w[2] = (int8_t)((q >> 16) & 0xff); w[3] = (int8_t)((uint32_t)q >> 24);
+  }
+  v[0] = ok ? w[0] : 0;
+  v[1] = ok ? w[1] : 0;
+  v[2] = ok ? w[2] : 0;
+  v[3] = ok ? w[3] : 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void st4_nt(T* base, int64_t off, const int64_t (&v)[4]) {
+  T* p = base + off;
+  if (sizeof(T) == 4) {
+    const v4i32 q = {(int32_t)v[0], (int32_t)v[1], (int32_t)v[2], (int32_t)v[3]};
+    __builtin_nontemporal_store(q, reinterpret_cast<v4i32*>(p));
+  } else if (sizeof(T) == 2) {
+    const v2i32 q = {(int32_t)((uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16)),
+                     (int32_t)((uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16))};
+    __builtin_nontemporal_store(q, reinterpret_cast<v2i32*>(p));
+  } else {
+    const int q = (int)((uint32_t)(uint8_t)v[0] | ((uint32_t)(uint8_t)v[1] << 8) |
+                        ((uint32_t)(uint8_t)v[2] << 16) | ((uint32_t)(uint8_t)v[3] << 24));
+    __builtin_nontemporal_store(q, reinterpret_cast<int*>(p));
+  }
+}
+
 // Epilogue variants chosen once per launch, outside the loops:
 //   kVarFastA1 — fast path and alpha = 1 (a = g, no multiply),
 //   kVarFast   — fast path, general alpha,

@@ -28,6 +28,8 @@ struct StarLaunch {
   int xbits, ybits, zbits;
   int wide;   // 1: accumulate the stencil sum in int64
   int rows;   // rows (2D) or planes (3D) marched by one wave
+  int wx;     // 2D: column segments per block (1, 2 or 4; the block's 4 waves
+              // cover wx segments times 4 / wx row bands)
 };
 hipError_t launch_star(const StarLaunch& L, hipStream_t s);
 

@@ -33,9 +33,10 @@ def test_every_declared_function_is_exported_and_bound():
 
 
 def test_layout():
-    assert P.bfp_layout(2, 4095, 32) == (4100, 4100 * 4097 * 4)
-    assert P.bfp_layout(2, 31, 16) == (40, 40 * 33 * 2)
-    assert P.bfp_layout(3, 511, 8) == (528, 528 * 513 * 513)
+    assert P.bfp_layout(2, 4095, 32) == (4128, 4128 * 4097 * 4)
+    assert P.bfp_layout(2, 31, 16) == (64, 64 * 33 * 2)
+    assert P.bfp_layout(3, 511, 8) == (640, 640 * 513 * 513)
+    assert P.bfp_layout(2, 30, 32) == (32, 32 * 32 * 4)
     with pytest.raises(P.BFPError):
         P.bfp_layout(4, 7, 32)
     with pytest.raises(P.BFPError):

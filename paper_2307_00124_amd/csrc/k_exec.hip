@@ -146,31 +146,37 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   const int M = (1 << lg) - 1;
   const int tot = ND == 3 ? 1 << (3 * lg) : 1 << (2 * lg);
   const int64_t side = n + 2;
-  for (int i0 = threadIdx.x; i0 < tot; i0 += U * NT) {
-    int64_t g[U], zo[U];
-    int32_t yv[U];
-    bool ok[U];
+  auto body = [&](auto var_tag) {
+    constexpr int VAR = decltype(var_tag)::value;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += U * NT) {
+      int64_t g[U], zo[U];
+      int32_t yv[U];
+      bool ok[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * NT;
-      int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
-      ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
-      if (!ok[u]) {
-        x = 1;
-        y = 1;
-        z = ND == 3 ? 1 : 0;
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
+        ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
+        if (!ok[u]) {
+          x = 1;
+          y = 1;
+          z = ND == 3 ? 1 : 0;
+        }
+        const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
+        g[u] = gather(z, y, x);
+        zo[u] = row * pz + x;
+        yv[u] = HASY ? ldx(ys, row * py + x) : 0;
       }
-      const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
-      g[u] = gather(z, y, x);
-      zo[u] = row * pz + x;
-      yv[u] = HASY ? ldx(ys, row * py + x) : 0;
-    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t v = E.template put<kVarGen>(g[u], yv[u], ok[u]);
-      if (PASS != kQ1 && ok[u]) stv(zp, zbits, zo[u], v);
+      for (int u = 0; u < U; ++u) {
+        const int64_t v = E.template put<VAR>(g[u], yv[u], ok[u]);
+        if (PASS != kQ1 && ok[u]) stv(zp, zbits, zo[u], v);
+      }
     }
-  }
+  };
+  // the fast epilogue when no intermediate can overflow (decided once per op)
+  if (PASS != kQ1 && E.fast) body(std::integral_constant<int, kVarFast>());
+  else body(std::integral_constant<int, kVarGen>());
   ex_finish<NT>(E, ma.lm[ma.s[kOpZ]]);
 }
 

@@ -62,7 +62,9 @@ def parse():
     ap.add_argument("--level3d", type=int, default=9, help="3D solve level (0: skip)")
     ap.add_argument("--serve", type=int, default=2000,
                     help="requests of the serving trace (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for this process (0: leave the environment's)")
     ap.add_argument("--only", choices=["all", "kernel", "copy"], default="all",
                     help="kernel: only the dominant-kernel loop (for profiler runs); copy: only "
                          "a plain 1 GiB device copy (counter calibration)")
@@ -75,6 +77,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solves of "
               "this workload are single-GPU and no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
+    # the request server overlaps its slots only as far as HIP has hardware
+    # queues (HIP's default is 4); must be set before HIP initializes
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import numpy as np
     import torch
 

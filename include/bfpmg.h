@@ -358,11 +358,18 @@ int mg_batch_counters(const mg_batch* b, double* bytes, int64_t* launches);
  * on any other stream: a request's buffers must be ready (the work that
  * fills them finished) when it is submitted. Hierarchy creation on first
  * use of a parameter set synchronizes that slot's stream. Not thread-safe:
- * one host thread drives a server.                                       */
+ * one host thread drives a server. Slots overlap only as far as the HIP
+ * runtime has hardware queues: set GPU_MAX_HW_QUEUES (HIP's default is 4)
+ * before the process initializes HIP; 16 queues with 16 slots measured
+ * best on MI355X.                                                        */
 typedef struct mg_server mg_server;
 typedef struct {
   int32_t max_slots;   /* requests on the device at once, 1..64            */
   int32_t max_queue;   /* queued requests beyond which submit is BFP_EBUSY  */
+  int32_t exec_max_points; /* levels with at most this many points run in
+                              the one-workgroup recorded programs of the
+                              server's hierarchies; 0 = 70000 (2D up to
+                              255^2, 3D up to 31^3)                        */
 } mg_server_cfg;
 typedef struct {
   mg_params prm;                          /* shape, widths, schedule       */

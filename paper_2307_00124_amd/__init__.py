@@ -392,11 +392,11 @@ class Server:
     (mg_server_* calls). submit() returns a ticket; poll() never blocks."""
 
     def __init__(self, budget: int, max_slots: int = 8, max_queue: int = 1 << 20,
-                 device="cuda"):
+                 exec_max_points: int = 0, device="cuda"):
         self.arena = torch.empty(budget + 256, dtype=torch.uint8, device=device)
         off = (-self.arena.data_ptr()) % 256
         self.arena = self.arena[off:off + budget]
-        cfg = abi.mg_server_cfg(max_slots, max_queue)
+        cfg = abi.mg_server_cfg(max_slots, max_queue, exec_max_points)
         s = C.c_void_p()
         check(lib.mg_server_create(C.byref(cfg), _ptr(self.arena), budget, C.byref(s)),
               "mg_server_create")

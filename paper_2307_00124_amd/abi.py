@@ -55,7 +55,8 @@ class mg_params(C.Structure):
 
 
 class mg_server_cfg(C.Structure):
-    _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32)]
+    _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32),
+                ("exec_max_points", C.c_int32)]
 
 
 class mg_request(C.Structure):

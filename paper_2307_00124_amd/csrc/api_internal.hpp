@@ -50,6 +50,12 @@ int to_f64_impl(const bfp_vec* src, double* dst_dev, double* const* table_dev, i
 int set_rhs_table(mg_hierarchy* h, int level, const double* const* table_dev, int index,
                   hipStream_t s);
 
+// mg_hierarchy_bytes / mg_hierarchy_create with an explicit executor
+// threshold (largest grid, in points, run inside recorded programs)
+int hierarchy_bytes_ex(const mg_params* prm, int64_t exec_points, size_t* bytes);
+int hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
+                        int64_t exec_points, mg_hierarchy** out);
+
 // validation of multigrid parameters (BFP_OK or the error of mg_params checks)
 int params_ok(const mg_params* p);
 

@@ -276,8 +276,7 @@ int fmg_levels(mg_hierarchy* h, int lo, int hi, hipStream_t s) {
 }
 
 // levels whose grids fit the coarse-level executor
-int exec_levels(const mg_params* p) {
-  const int64_t maxp = exec_max_points();
+int exec_levels(const mg_params* p, int64_t maxp) {
   int lc = 0;
   for (int j = 1; j <= p->L; ++j) {
     const int64_t n = ((int64_t)1 << j) - 1;
@@ -372,7 +371,7 @@ size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops) {
 
 // Host-side set-up shared by sizing and creation: stencils, the exact
 // (2 c1 + 1) / 4, the executor levels.
-int setup(mg_hierarchy* h, const mg_params* prm) {
+int setup(mg_hierarchy* h, const mg_params* prm, int64_t exec_points) {
   h->prm = *prm;
   make_stencils(prm->ndim, &h->A, &h->R, &h->P);
   // (2 c1 + 1) / 4 exactly: c1 = m 2^e
@@ -387,16 +386,16 @@ int setup(mg_hierarchy* h, const mg_params* prm) {
   h->vres.w = 24;
   while (h->vres.m % 2 == 0) { h->vres.m /= 2; h->vres.exp += 1; }
   if (h->vres.m >= (1 << 23)) return fail(BFP_EWIDTH, "(2 c1 + 1) / 4 needs more than 24 bits");
-  h->Lc = exec_levels(prm);
+  h->Lc = exec_levels(prm, exec_points);
   return BFP_OK;
 }
 
 // Number of recorded operations the hierarchy's programs hold: recorded
 // on a layout at a stand-in address, with no device work.
-int count_ops(const mg_params* prm, size_t* nops) {
+int count_ops(const mg_params* prm, int64_t exec_points, size_t* nops) {
   mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
   if (!h) return fail(BFP_ENOMEM, "host allocation failed");
-  int rc = setup(h, prm);
+  int rc = setup(h, prm, exec_points);
   if (!rc) {
     layout(h, prm, reinterpret_cast<char*>((uintptr_t)1 << 20), 0);
     std::vector<ExecOp> V, F;
@@ -512,7 +511,7 @@ int plan_batch(mg_batch* B, const mg_params* prms, int nprob, char* arena, size_
       B->groups.push_back(g);
       gi = (int)B->groups.size() - 1;
       BatchGroup& G = B->groups.back();
-      if ((rc = setup(G.h, &G.prm))) return rc;
+      if ((rc = setup(G.h, &G.prm, 0))) return rc;
       G.h->Lc = 0;
       G.region = layout(G.h, &G.prm, reinterpret_cast<char*>(kStandIn), 0);
       if ((rc = record_batch_program(G))) return rc;
@@ -626,24 +625,38 @@ int mg_params_init(int ndim, int L, int w, int progressive, int nu1, int nu2, in
 }
 
 size_t mg_hierarchy_bytes(const mg_params* prm) {
-  if (check_params(prm)) return 0;
-  size_t nops = 0;
-  if (count_ops(prm, &nops)) return 0;
-  mg_hierarchy tmp;
-  return layout(&tmp, prm, nullptr, nops);
+  size_t b = 0;
+  return hierarchy_bytes_ex(prm, exec_max_points(), &b) ? 0 : b;
 }
 
 int mg_hierarchy_create(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
                         mg_hierarchy** out) {
+  return hierarchy_create_ex(prm, arena_dev, bytes, stream, exec_max_points(), out);
+}
+
+}  // extern "C"
+
+int bfpk::hierarchy_bytes_ex(const mg_params* prm, int64_t exec_points, size_t* bytes) {
+  int rc = check_params(prm);
+  if (rc) return rc;
+  size_t nops = 0;
+  if ((rc = count_ops(prm, exec_points, &nops))) return rc;
+  mg_hierarchy tmp;
+  *bytes = layout(&tmp, prm, nullptr, nops);
+  return BFP_OK;
+}
+
+int bfpk::hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
+                              int64_t exec_points, mg_hierarchy** out) {
   int rc = check_params(prm);
   if (rc) return rc;
   if (!out || !arena_dev) return fail(BFP_EINVAL, "NULL argument");
   if ((uintptr_t)arena_dev % 256) return fail(BFP_EINVAL, "arena must be 256-byte aligned");
   size_t nops = 0;
-  if ((rc = count_ops(prm, &nops))) return rc;
+  if ((rc = count_ops(prm, exec_points, &nops))) return rc;
   mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
   if (!h) return fail(BFP_ENOMEM, "host allocation failed");
-  if ((rc = setup(h, prm))) { delete h; return rc; }
+  if ((rc = setup(h, prm, exec_points))) { delete h; return rc; }
   const size_t need = layout(h, prm, nullptr, nops);
   if (bytes < need) {
     delete h;
@@ -690,6 +703,8 @@ int mg_hierarchy_create(const mg_params* prm, void* arena_dev, size_t bytes, voi
   *out = h;
   return BFP_OK;
 }
+
+extern "C" {
 
 int mg_hierarchy_destroy(mg_hierarchy* h) {
   delete h;

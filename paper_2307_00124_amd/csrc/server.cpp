@@ -68,10 +68,20 @@ struct Queued {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Default executor threshold of the server's hierarchies: 2D grids up to
+// 255^2 and 3D grids up to 31^3 run entirely inside one recorded program.
+// Measured on MI355X with the serving trace: throughput is bounded by kernel
+// dispatch rather than by compute when each request issues ~100 launches,
+// so running more levels in one workgroup per request (fewer launches,
+// longer single-request latency) keeps up with 2000 requests/s where the
+// 4096-point default falls behind.
+constexpr int64_t kServerExecPoints = 70000;
+
 }  // namespace
 
 struct mg_server {
   mg_server_cfg cfg;
+  int64_t exec_points = 0;
   char* arena = nullptr;
   size_t bytes = 0;
   std::vector<Resident> pool;
@@ -143,10 +153,13 @@ struct mg_server {
   // created after evicting idle ones (least recently used first); -1 when
   // the arena cannot hold it now
   int resident_for(const mg_params& p, hipStream_t s, int* rc) {
+    const int64_t exec_points = this->exec_points;
     *rc = BFP_OK;
     for (size_t i = 0; i < pool.size(); ++i)
       if (!pool[i].busy && !std::memcmp(&pool[i].prm, &p, sizeof p)) return (int)i;
-    const size_t hb = align256(mg_hierarchy_bytes(&p));
+    size_t hb0 = 0;
+    if ((*rc = hierarchy_bytes_ex(&p, exec_points, &hb0))) return -1;
+    const size_t hb = align256(hb0);
     const size_t need = hb + kTableBytes;
     if (hb == 0 || need > bytes) {
       *rc = fail(BFP_ENOMEM, "a request needs %zu bytes of the %zu-byte arena", need, bytes);
@@ -170,7 +183,8 @@ struct mg_server {
     r.off = off;
     r.size = need;
     r.table = (const double**)(arena + off + hb);
-    if ((*rc = mg_hierarchy_create(&p, arena + off, hb, s, &r.h)) || (*rc = capture(r, s))) {
+    if ((*rc = hierarchy_create_ex(&p, arena + off, hb, s, exec_points, &r.h)) ||
+        (*rc = capture(r, s))) {
       if (r.h) drop(r);
       release(off, need);
       return -1;
@@ -250,6 +264,7 @@ int mg_server_create(const mg_server_cfg* cfg, void* arena_dev, size_t bytes, mg
   mg_server* s = new (std::nothrow) mg_server();
   if (!s) return fail(BFP_ENOMEM, "host allocation failed");
   s->cfg = *cfg;
+  s->exec_points = cfg->exec_max_points > 0 ? cfg->exec_max_points : kServerExecPoints;
   s->arena = static_cast<char*>(arena_dev);
   s->bytes = bytes & ~(size_t)255;
   s->free_ranges.emplace_back(0, s->bytes);

@@ -202,6 +202,13 @@ def main():
                                                  gz, zs, stream), args.kernel_reps)
     stencils["5pt_4095sq_int32"] = {"avg_us": round(t2, 2), "bytes": dof * 8.0,
                                     "gbs": round(dof * 8.0 / (t2 * 1e-6) / 1e9, 1)}
+    # a plain device copy of the same bytes (torch), the practical ceiling
+    ca = torch.ones(dof * 4, dtype=torch.int32, device=dev)
+    cb = torch.empty_like(ca)
+    tcp = time_kernel(lambda: cb.copy_(ca), args.kernel_reps)
+    stencils["copy_8x4095sq_int32"] = {"avg_us": round(tcp, 2), "bytes": dof * 32.0,
+                                       "gbs": round(dof * 32.0 / (tcp * 1e-6) / 1e9, 1)}
+    del ca, cb
     del xs, zs
     if not args.no_3d:
         n3 = 511
@@ -221,6 +228,9 @@ def main():
                                          "gbs": round(d3 * 8.0 / (t3 * 1e-6) / 1e9, 1)}
         del x3, z3
         torch.cuda.empty_cache()
+
+    # -------------------------------------------------- 33x33 latency ---
+    c1 = bench_c1(P, W, torch, dev, stream, ev)
 
     # ------------------------------------------------------- 3D solve ---
     solve3d = None
@@ -307,6 +317,7 @@ def main():
         "bfp_over_fp64_dof_per_s": round((dof / (ms * 1e-3)) / fp64["dof_per_s"], 2),
         "stencil_apply": stencils,
         "solve_3d": solve3d,
+        "c1_33x33": c1,
         "sweep": sweep,
         "batched": batch,
         "serving": serving,
@@ -465,6 +476,36 @@ def bench_fp64(P, torch, f, L, us, h2, disc, stream, ev):
     return {"what": "FP64 FMG, same schedule and coefficients, torch tensor ops on the same GPU",
             "ms": round(ms, 3), "dof_per_s": dof / (ms * 1e-3),
             "err_over_disc": round(err / disc, 4)}
+
+
+def bench_c1(P, W, torch, dev, stream, ev):
+    """The 33 x 33 problem (5 levels, widths 32): latency of one FMG with
+    N = 2 IR-V(2,2) (qcomp) and of 10 IR-V(2,2) iterations from the seeded
+    random initial guess, on one stream."""
+    p = P.mg_params_init(2, 5, 32, False, 2, 2, 2, P.MG_POLICY_Q, 13)
+    H = P.Hierarchy(p)
+    for j in range(1, 6):
+        H.set_rhs(j, torch.from_numpy(W.manufactured_f(j, 2)).to(dev), stream)
+    x0 = torch.from_numpy(W.initial_guess(5, 2, seed=0)).to(dev)
+
+    def lat(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1000.0 / reps
+
+    def ir10():
+        H.set_x(5, x0, stream)
+        H.ir(5, 10, stream)
+
+    return {"workload": "2D 33x33, 5 levels, widths 32, qcomp", "fmg_n2_v22_us": round(lat(lambda: H.fmg(stream)), 1),
+            "ir10_v22_from_random_us": round(lat(ir10), 1)}
 
 
 def bench_3d(args, P, W, torch, dev, stream, ev):

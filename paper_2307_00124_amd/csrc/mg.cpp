@@ -39,6 +39,10 @@ struct Level {
 
 }  // namespace
 
+namespace {
+enum { kPV = 0, kPF = 1, kPI1 = 2, kPI2 = 3, kPIn = 4, kPrograms = 5 };
+}
+
 // A recorded coarse-level program: ops in the arena, run by one launch of
 // the executor; `bytes` is the algorithmic traffic of the ops it stands for.
 struct Program {
@@ -57,8 +61,10 @@ struct mg_hierarchy {
   double bytes;
   int64_t launches;
   int Lc;               // levels 1..Lc run inside the programs (0: none)
-  Program progV;        // V-cycle on level Lc from its restricted residual vr
-  Program progF;        // FMG on levels 1..Lc (from x_1 = 0)
+  // recorded programs: the V-cycle on level Lc from its restricted residual
+  // vr, FMG on levels 1..Lc (from x_1 = 0), and IR-V iterations on level Lc
+  // (the first, the second, any later one)
+  Program prog[kPrograms];
 };
 
 namespace {
@@ -186,9 +192,9 @@ int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
   Level& L = h->lv[l];
   const mg_params& p = h->prm;
   int rc;
-  if (!recording() && l == h->Lc && h->progV.count && rin.mant == L.vr.mant &&
+  if (!recording() && l == h->Lc && h->prog[kPV].count && rin.mant == L.vr.mant &&
       rin.meta == L.vr.meta)
-    return run_program(h, h->progV, s);
+    return run_program(h, h->prog[kPV], s);
   // relaxation from y = 0: y = c2 A r + c1 r
   if ((rc = op_stencil(h, &h->A, rin, &p.c2, &p.c1, &rin, L.y, mode_for(h, kRelax, false),
                        g_norm(rin, p.c1), s)))
@@ -288,25 +294,38 @@ int exec_levels(const mg_params* p, int64_t maxp) {
 }
 
 // Record the coarse-level programs of a laid-out hierarchy (no device work):
-// the V-cycle on level Lc from vr and FMG on levels 1..Lc, through the same
-// code that otherwise launches each operation.
-int record_programs(mg_hierarchy* h, std::vector<ExecOp>* V, std::vector<ExecOp>* F,
-                    double* bytesV, double* bytesF) {
-  V->clear();
-  F->clear();
+// the V-cycle on level Lc from vr, FMG on levels 1..Lc and the first, second
+// and any later IR-V iteration on level Lc, through the same code that
+// otherwise launches each operation.
+int record_programs(mg_hierarchy* h, std::vector<ExecOp> (&P)[kPrograms],
+                    double (&bytes)[kPrograms]) {
+  for (int k = 0; k < kPrograms; ++k) {
+    P[k].clear();
+    bytes[k] = 0;
+  }
   if (h->Lc == 0) return BFP_OK;
   const double b0 = h->bytes;
   const int64_t l0 = h->launches;
-  record_into(V);
-  int rc = vcycle(h, h->Lc, h->lv[h->Lc].vr, nullptr);
-  const double b1 = h->bytes;
-  if (!rc) {
-    record_into(F);
-    rc = fmg_levels(h, 1, h->Lc, nullptr);
+  const int Lc = h->Lc;
+  Level& L = h->lv[Lc];
+  int rc = BFP_OK;
+  for (int k = 0; k < kPrograms && !rc; ++k) {
+    const double before = h->bytes;
+    record_into(&P[k]);
+    if (k == kPV) {
+      rc = vcycle(h, Lc, L.vr, nullptr);
+    } else if (k == kPF) {
+      rc = fmg_levels(h, 1, Lc, nullptr);
+    } else {
+      // the i-th IR-V iteration on level Lc as mg_ir issues it (i = 1, 2, >2)
+      const int i = k - kPI1 + 1;
+      bfp_gamma g = g_norm(L.r, kOne);
+      const bool plain_first2 = h->prm.policy == MG_POLICY_NN_IR_FIRST2_Q && i <= 2;
+      rc = ir_iteration(h, Lc, i == 1 ? nullptr : &g, i == 1, plain_first2, nullptr);
+    }
+    record_into(nullptr);
+    bytes[k] = h->bytes - before;
   }
-  record_into(nullptr);
-  *bytesV = b1 - b0;
-  *bytesF = h->bytes - b1;
   h->bytes = b0;
   h->launches = l0;
   return rc;
@@ -361,10 +380,10 @@ size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops) {
       off = align256(off + kMetaSlots * sizeof(int64_t));
     }
   }
-  h->progV.metas = base ? (int64_t**)(base + off) : nullptr;
-  h->progF.metas = base ? (int64_t**)(base + off) + kExecMaxMeta : nullptr;
-  off = align256(off + 2 * kExecMaxMeta * sizeof(int64_t*));
-  h->progV.ops = base ? (ExecOp*)(base + off) : nullptr;
+  for (int k = 0; k < kPrograms; ++k)
+    h->prog[k].metas = base ? (int64_t**)(base + off) + k * kExecMaxMeta : nullptr;
+  off = align256(off + kPrograms * kExecMaxMeta * sizeof(int64_t*));
+  h->prog[0].ops = base ? (ExecOp*)(base + off) : nullptr;
   off = align256(off + nops * sizeof(ExecOp));
   return off;
 }
@@ -398,10 +417,11 @@ int count_ops(const mg_params* prm, int64_t exec_points, size_t* nops) {
   int rc = setup(h, prm, exec_points);
   if (!rc) {
     layout(h, prm, reinterpret_cast<char*>((uintptr_t)1 << 20), 0);
-    std::vector<ExecOp> V, F;
-    double bv, bf;
-    rc = record_programs(h, &V, &F, &bv, &bf);
-    *nops = V.size() + F.size();
+    std::vector<ExecOp> Pg[kPrograms];
+    double bytes[kPrograms];
+    rc = record_programs(h, Pg, bytes);
+    *nops = 0;
+    for (auto& v : Pg) *nops += v.size();
   }
   delete h;
   return rc;
@@ -670,32 +690,35 @@ int bfpk::hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t byte
       if ((rc = bfp_vec_init(v, stream))) { delete h; return rc; }
     }
   }
-  std::vector<ExecOp> V, F;
-  std::vector<int64_t*> mV, mF;
-  if ((rc = record_programs(h, &V, &F, &h->progV.bytes, &h->progF.bytes)) ||
-      (rc = exec_assign_slots(V, mV)) || (rc = exec_assign_slots(F, mF))) {
+  std::vector<ExecOp> Pg[kPrograms];
+  std::vector<int64_t*> M[kPrograms];
+  double pbytes[kPrograms];
+  rc = record_programs(h, Pg, pbytes);
+  for (int k = 0; k < kPrograms && !rc; ++k) rc = exec_assign_slots(Pg[k], M[k]);
+  if (rc) {
     delete h;
     return rc;
   }
-  if (V.size() + F.size() != nops) {
-    delete h;
-    return fail(BFP_EINVAL, "recorded programs changed size (%zu vs %zu ops)", V.size() + F.size(), nops);
+  std::vector<ExecOp> all;
+  std::vector<int64_t*> tables(kPrograms * kExecMaxMeta, nullptr);
+  for (int k = 0; k < kPrograms; ++k) {
+    Program& pg = h->prog[k];
+    pg.ops = h->prog[0].ops + all.size();
+    pg.count = (int)Pg[k].size();
+    pg.nmeta = (int)M[k].size();
+    pg.bytes = pbytes[k];
+    all.insert(all.end(), Pg[k].begin(), Pg[k].end());
+    std::copy(M[k].begin(), M[k].end(), tables.begin() + k * kExecMaxMeta);
   }
-  h->progV.count = (int)V.size();
-  h->progV.nmeta = (int)mV.size();
-  h->progF.ops = h->progV.ops + V.size();
-  h->progF.count = (int)F.size();
-  h->progF.nmeta = (int)mF.size();
+  if (all.size() != nops) {
+    delete h;
+    return fail(BFP_EINVAL, "recorded programs changed size (%zu vs %zu ops)", all.size(), nops);
+  }
   if (nops) {
-    std::vector<ExecOp> all(V);
-    all.insert(all.end(), F.begin(), F.end());
-    std::vector<int64_t*> tables(2 * kExecMaxMeta, nullptr);
-    std::copy(mV.begin(), mV.end(), tables.begin());
-    std::copy(mF.begin(), mF.end(), tables.begin() + kExecMaxMeta);
-    rc = hip_check(hipMemcpyAsync(h->progV.ops, all.data(), nops * sizeof(ExecOp),
+    rc = hip_check(hipMemcpyAsync(h->prog[0].ops, all.data(), nops * sizeof(ExecOp),
                                   hipMemcpyHostToDevice, s), "program upload");
     if (!rc)
-      rc = hip_check(hipMemcpyAsync(h->progV.metas, tables.data(), tables.size() * sizeof(int64_t*),
+      rc = hip_check(hipMemcpyAsync(h->prog[0].metas, tables.data(), tables.size() * sizeof(int64_t*),
                                     hipMemcpyHostToDevice, s), "program upload");
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "program upload");
     if (rc) { delete h; return rc; }
@@ -734,7 +757,14 @@ int mg_ir(mg_hierarchy* h, int level, int iters, void* stream) {
   if (!h || level < 1 || level > h->prm.L || iters < 0) return fail(BFP_EINVAL, "bad argument");
   hipStream_t s = (hipStream_t)stream;
   Level& L = h->lv[level];
+  // level Lc: the recorded IR-V programs (first, second, later iterations)
+  const bool progs = !recording() && level == h->Lc && h->prog[kPI1].count;
   for (int i = 1; i <= iters; ++i) {
+    if (progs) {
+      int rc = run_program(h, h->prog[kPI1 + std::min(i, 3) - 1], s);
+      if (rc) return rc;
+      continue;
+    }
     bfp_gamma g = g_norm(L.r, kOne);
     const bool plain_first2 = h->prm.policy == MG_POLICY_NN_IR_FIRST2_Q && i <= 2;
     int rc = ir_iteration(h, level, i == 1 ? nullptr : &g, i == 1, plain_first2, s);
@@ -748,8 +778,8 @@ int mg_fmg(mg_hierarchy* h, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   int rc;
   int lo = 1;
-  if (h->progF.count) {
-    if ((rc = run_program(h, h->progF, s))) return rc;
+  if (h->prog[kPF].count) {
+    if ((rc = run_program(h, h->prog[kPF], s))) return rc;
     lo = h->Lc + 1;
   }
   return fmg_levels(h, lo, h->prm.L, s);

@@ -189,3 +189,31 @@ def test_coarse_programs_match_launches(ndim, L, w, prog, policy, nu):
     b0, l0 = H0.counters()
     b1, l1 = H1.counters()
     assert abs(b0 - b1) <= 1e-9 * b0 and l1 < l0
+
+
+@pytest.mark.parametrize("ndim,L,w,prog,policy,nu", [
+    (2, 5, 32, False, "q", (2, 2)), (2, 6, 24, True, "nn_ir_first2_q", (1, 1)),
+    (2, 6, 16, True, "nn_ir_first_q", (1, 0)), (3, 4, 20, True, "nn_ir_q", (2, 1))])
+def test_ir_programs_match_launches(ndim, L, w, prog, policy, nu):
+    """IR-V on a finest level small enough for the executor (each iteration
+    one recorded program: the first, the second and the later ones differ
+    in their compression modes) gives the same x and r, bit for bit, as
+    with one launch per operation; checked after 1 and after 4 iterations."""
+    x0 = torch.from_numpy(np.ascontiguousarray(W.initial_guess(L, ndim, seed=3))).cuda()
+    out = []
+    for pts in (0, 4096):
+        H = _lib_hierarchy(ndim, L, w, prog, policy, nu[0], nu[1], 2, 23, pts)
+        H.set_x(L, x0)
+        H.ir(L, 1)
+        one = (H.get_vec(L, 0).mantissas().clone(), H.get_vec(L, 0).host_meta()[:6])
+        H.set_x(L, x0)
+        H.ir(L, 4)
+        torch.cuda.synchronize()
+        out.append((H, one))
+    (H0, o0), (H1, o1) = out
+    assert torch.equal(o0[0], o1[0]) and o0[1] == o1[1], "x after one IR iteration"
+    _same_block(H0.get_vec(L, 0), H1.get_vec(L, 0), "x after 4 IR iterations")
+    _same_block(H0.get_vec(L, 2), H1.get_vec(L, 2), "r after 4 IR iterations")
+    b0, l0 = H0.counters()
+    b1, l1 = H1.counters()
+    assert abs(b0 - b1) <= 1e-9 * b0 and l1 == 5 < l0

@@ -152,9 +152,10 @@ def main():
     dot_out = torch.zeros(P.BFP_META_SLOTS, dtype=torch.int64, device=dev)
 
     def step(H, xout):
-        for j in range(1, L + 1):
-            H.set_rhs(j, f[j], stream)                  # FP64 -> BFP (b_j)
-        H.fmg(stream)                                   # FMG
+        # FP64 -> BFP (b_j on every level) and FMG, in one call: the coarse
+        # levels' quantization runs inside the coarse-level program, the
+        # finer levels' on a second stream meanwhile
+        H.fmg_f64(f[1:], stream)
         xl = H.get_vec(L, 0)
         P.bfp_normalize(xl, xl.w, xout, stream)         # normalized solution
         rl = H.get_vec(L, 2)

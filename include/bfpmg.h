@@ -301,6 +301,19 @@ int mg_set_x(mg_hierarchy* h, int level, const double* x0_dev, void* stream);
  * and N IR-V(nu1,nu2) iterations. Result in the level-L iterate.          */
 int mg_fmg(mg_hierarchy* h, void* stream);
 
+/* One whole solve from FP64 data: mg_set_rhs for every level j = 1..L with
+ * f_dev = rhs_dev[j-1] (a host array of L device pointers), then mg_fmg;
+ * results are identical to those calls. The levels the coarse-level program
+ * runs are quantized inside that program, and the finer levels on a second
+ * stream owned by the hierarchy (created on the first call, default
+ * priority) while the program runs; that stream starts after the work
+ * issued on `stream` so far, and `stream` waits for it before the finer
+ * levels' FMG, so the call is ordered on `stream` like the others.
+ * rhs_dev is read during the call only. Errors: BFP_EINVAL for a NULL
+ * argument or level pointer (nothing issued), BFP_EHIP if the stream or
+ * events cannot be created.                                              */
+int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream);
+
 /* `iters` IR-V(nu1,nu2) iterations on level `level` from its current x.   */
 int mg_ir(mg_hierarchy* h, int level, int iters, void* stream);
 

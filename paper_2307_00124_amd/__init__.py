@@ -308,12 +308,33 @@ class Hierarchy:
             lib.mg_hierarchy_destroy(h)
             self.h = None
 
-    def set_rhs(self, level: int, f: torch.Tensor, stream=None) -> None:
+    def _check_f64(self, level: int, f: torch.Tensor, what: str) -> None:
+        side = (1 << level) + 1
         if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous():
-            raise ValueError("f must be a contiguous float64 device tensor")
+            raise ValueError(f"{what} must be a contiguous float64 device tensor")
+        if f.numel() != side ** self.params.ndim:
+            raise ValueError(f"{what} must hold the padded level-{level} grid "
+                             f"({side}^{self.params.ndim} values), not {f.numel()}")
+
+    def set_rhs(self, level: int, f: torch.Tensor, stream=None) -> None:
+        if 1 <= level <= self.params.L:
+            self._check_f64(level, f, "f")
         check(lib.mg_set_rhs(self.h, level, _ptr(f), _stream(stream)), "mg_set_rhs")
 
+    def fmg_f64(self, rhs: list, stream=None) -> None:
+        """mg_fmg_f64: quantize the right-hand sides rhs[j-1] of levels
+        j = 1..L (FP64, padded grids) and run FMG, in one call."""
+        L = self.params.L
+        if len(rhs) != L:
+            raise ValueError(f"need {L} right-hand sides, got {len(rhs)}")
+        for j, f in enumerate(rhs, start=1):
+            self._check_f64(j, f, f"rhs[{j - 1}]")
+        ptrs = (C.c_void_p * L)(*[f.data_ptr() for f in rhs])
+        check(lib.mg_fmg_f64(self.h, ptrs, _stream(stream)), "mg_fmg_f64")
+
     def set_x(self, level: int, x0: torch.Tensor, stream=None) -> None:
+        if 1 <= level <= self.params.L:
+            self._check_f64(level, x0, "x0")
         check(lib.mg_set_x(self.h, level, _ptr(x0), _stream(stream)), "mg_set_x")
 
     def fmg(self, stream=None) -> None:

@@ -100,6 +100,7 @@ SIGNATURES = {
     "mg_set_rhs": (I, [VP, I, VP, VP]),
     "mg_set_x": (I, [VP, I, VP, VP]),
     "mg_fmg": (I, [VP, VP]),
+    "mg_fmg_f64": (I, [VP, VP, VP]),
     "mg_ir": (I, [VP, I, I, VP]),
     "mg_vcycle": (I, [VP, I, P(bfp_vec), P(bfp_vec), VP]),
     "mg_get_vec": (I, [VP, I, I, P(bfp_vec)]),

@@ -125,7 +125,9 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm)
       }
     }
   }
-  __syncthreads();
+  // the second qcomp pass reads mu* at once; after an output pass the
+  // program loop's barrier follows (red[] is next written after it)
+  if (PASS == kQ1) __syncthreads();
 }
 
 // Visit every interior point (z, y, x) of an n^ND output grid: the exact
@@ -466,8 +468,12 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
 template <int ND>
 __global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict__ ops, int count,
                                                       int64_t* const* __restrict__ metas,
-                                                      int nmeta) {
-  run_program<kExecThreads, ND>(ops, count, metas, nmeta, 0, nullptr);
+                                                      int nmeta, ExecRhs rhs) {
+  // the right-hand-side pointers, for the program's conversions (read after
+  // the program runner's first barrier)
+  __shared__ const double* srhs[kMaxLevels];
+  if (threadIdx.x < kMaxLevels) srhs[threadIdx.x] = rhs.p[threadIdx.x];
+  run_program<kExecThreads, ND>(ops, count, metas, nmeta, 0, srhs);
 }
 
 template <int ND>
@@ -495,13 +501,15 @@ hipError_t launch_exec_batch(const BatchEntry* entries_dev, int nentries, const 
 }
 
 hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_dev, int nmeta,
-                       int ndim, hipStream_t s) {
+                       int ndim, const ExecRhs* rhs, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (nmeta < 1 || nmeta > kExecMaxMeta) return hipErrorInvalidValue;
+  ExecRhs r{};
+  if (rhs) r = *rhs;
   if (ndim == 2)
-    hipLaunchKernelGGL(k_exec<2>, dim3(1), dim3(kExecThreads), 0, s, ops_dev, count, metas_dev, nmeta);
+    hipLaunchKernelGGL(k_exec<2>, dim3(1), dim3(kExecThreads), 0, s, ops_dev, count, metas_dev, nmeta, r);
   else
-    hipLaunchKernelGGL(k_exec<3>, dim3(1), dim3(kExecThreads), 0, s, ops_dev, count, metas_dev, nmeta);
+    hipLaunchKernelGGL(k_exec<3>, dim3(1), dim3(kExecThreads), 0, s, ops_dev, count, metas_dev, nmeta, r);
   return hipGetLastError();
 }
 

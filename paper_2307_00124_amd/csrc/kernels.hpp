@@ -150,8 +150,14 @@ constexpr int kExecThreads = 512;
 constexpr int kExecMaxN = 1024;
 constexpr int kExecMaxMeta = 64;
 constexpr int kExMetaF = 8;
+// rhs: the FP64 right-hand sides of levels 1..kMaxLevels (device pointers,
+// passed by value in the launch) that the program's conversions read; may
+// be null when the program has none.
+struct ExecRhs {
+  const double* p[16];
+};
 hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_dev, int nmeta,
-                       int ndim, hipStream_t s);
+                       int ndim, const ExecRhs* rhs, hipStream_t s);
 
 // Batched programs: one workgroup of kBatchThreads threads per problem runs
 // that problem's program. Programs are relocatable: every data and metadata
@@ -160,6 +166,7 @@ hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_d
 // right-hand side on level j.
 constexpr int kBatchThreads = 256;
 constexpr int kMaxLevels = 16;
+static_assert(sizeof(ExecRhs) == kMaxLevels * sizeof(const double*), "one pointer per level");
 struct BatchEntry {
   uintptr_t base;        // the problem's arena base
   int prob;              // row of the right-hand-side table

@@ -40,7 +40,7 @@ struct Level {
 }  // namespace
 
 namespace {
-enum { kPV = 0, kPF = 1, kPI1 = 2, kPI2 = 3, kPIn = 4, kPrograms = 5 };
+enum { kPV = 0, kPF = 1, kPI1 = 2, kPI2 = 3, kPIn = 4, kPFc = 5, kPrograms = 6 };
 }
 
 // A recorded coarse-level program: ops in the arena, run by one launch of
@@ -62,12 +62,26 @@ struct mg_hierarchy {
   int64_t launches;
   int Lc;               // levels 1..Lc run inside the programs (0: none)
   // recorded programs: the V-cycle on level Lc from its restricted residual
-  // vr, FMG on levels 1..Lc (from x_1 = 0), and IR-V iterations on level Lc
-  // (the first, the second, any later one)
+  // vr, FMG on levels 1..Lc (from x_1 = 0), IR-V iterations on level Lc
+  // (the first, the second, any later one), and FMG on levels 1..Lc that
+  // first quantizes those levels' right-hand sides from FP64
   Program prog[kPrograms];
+  // mg_fmg_f64: a second stream (created on first use) that quantizes the
+  // finer levels' right-hand sides while the program runs the coarse ones
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~mg_hierarchy() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 namespace {
+
+// b_j = S_j^-1 f_j: the scaling of level j's FP64 right-hand side, a power
+// of two (h_j^2 / 4 in 2D, h_j^2 / 8 in 3D with h_j = 2^-j)
+int64_t rhs_shift(int ndim, int j) { return ndim == 2 ? -2 * j - 2 : -2 * j - 3; }
 
 int storage_for(int w, int min_bits) {
   int b = w <= 8 ? 8 : (w <= 16 ? 16 : 32);
@@ -178,8 +192,9 @@ int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, int 
   return BFP_OK;
 }
 
-int run_program(mg_hierarchy* h, const Program& pg, hipStream_t s) {
-  int rc = hip_check(launch_exec(pg.ops, pg.count, pg.metas, pg.nmeta, h->prm.ndim, s),
+int run_program(mg_hierarchy* h, const Program& pg, hipStream_t s,
+                const ExecRhs* rhs = nullptr) {
+  int rc = hip_check(launch_exec(pg.ops, pg.count, pg.metas, pg.nmeta, h->prm.ndim, rhs, s),
                      "coarse-level program");
   if (rc) return rc;
   h->bytes += pg.bytes;
@@ -294,9 +309,11 @@ int exec_levels(const mg_params* p, int64_t maxp) {
 }
 
 // Record the coarse-level programs of a laid-out hierarchy (no device work):
-// the V-cycle on level Lc from vr, FMG on levels 1..Lc and the first, second
-// and any later IR-V iteration on level Lc, through the same code that
-// otherwise launches each operation.
+// the V-cycle on level Lc from vr, FMG on levels 1..Lc, the first, second
+// and any later IR-V iteration on level Lc, and FMG on levels 1..Lc after
+// quantizing b_1..b_Lc from FP64 (each conversion the bfp_vec_from_f64 that
+// mg_set_rhs issues), through the same code that otherwise launches each
+// operation.
 int record_programs(mg_hierarchy* h, std::vector<ExecOp> (&P)[kPrograms],
                     double (&bytes)[kPrograms]) {
   for (int k = 0; k < kPrograms; ++k) {
@@ -315,6 +332,17 @@ int record_programs(mg_hierarchy* h, std::vector<ExecOp> (&P)[kPrograms],
     if (k == kPV) {
       rc = vcycle(h, Lc, L.vr, nullptr);
     } else if (k == kPF) {
+      rc = fmg_levels(h, 1, Lc, nullptr);
+    } else if (k == kPFc) {
+      for (int j = 1; j <= Lc; ++j) {
+        const bfp_vec& b = h->lv[j].b;
+        ExecOp e;
+        std::memset(&e, 0, sizeof e);
+        e.kind = kExConv;
+        e.u.conv = ConvOp{nullptr, b.mant, b.meta, b.ndim, b.n, b.pitch, b.storage_bits, b.w,
+                          rhs_shift(h->prm.ndim, j), j};
+        P[k].push_back(e);
+      }
       rc = fmg_levels(h, 1, Lc, nullptr);
     } else {
       // the i-th IR-V iteration on level Lc as mg_ir issues it (i = 1, 2, >2)
@@ -463,7 +491,7 @@ int record_batch_program(BatchGroup& g) {
     std::memset(&e, 0, sizeof e);
     e.kind = kExConv;
     e.u.conv = ConvOp{nullptr, b.mant, b.meta, b.ndim, b.n, b.pitch, b.storage_bits, b.w,
-                      (int64_t)(p.ndim == 2 ? -2 * j - 2 : -2 * j - 3), j};
+                      rhs_shift(p.ndim, j), j};
     g.ops.push_back(e);
     h->bytes += pts(b) * (8.0 + sz(b));
   }
@@ -736,7 +764,7 @@ int mg_hierarchy_destroy(mg_hierarchy* h) {
 
 int mg_set_rhs(mg_hierarchy* h, int level, const double* f_dev, void* stream) {
   if (!h || level < 1 || level > h->prm.L) return fail(BFP_EINVAL, "bad level");
-  const int64_t shift = h->prm.ndim == 2 ? -2 * level - 2 : -2 * level - 3;
+  const int64_t shift = rhs_shift(h->prm.ndim, level);
   return bfp_vec_from_f64(f_dev, shift, &h->lv[level].b, stream);
 }
 
@@ -783,6 +811,42 @@ int mg_fmg(mg_hierarchy* h, void* stream) {
     lo = h->Lc + 1;
   }
   return fmg_levels(h, lo, h->prm.L, s);
+}
+
+int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream) {
+  if (!h || !rhs_dev) return fail(BFP_EINVAL, "NULL argument");
+  const int L = h->prm.L, Lc = h->Lc;
+  for (int j = 1; j <= L; ++j)
+    if (!rhs_dev[j - 1]) return fail(BFP_EINVAL, "right-hand side of level %d is NULL", j);
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  const Program& pc = h->prog[kPFc];
+  if (!pc.count) {   // no executor levels: quantize every level, then FMG
+    for (int j = 1; j <= L; ++j)
+      if ((rc = mg_set_rhs(h, j, rhs_dev[j - 1], stream))) return rc;
+    return mg_fmg(h, stream);
+  }
+  if (Lc < L) {
+    // levels Lc+1..L are quantized on the side stream, after everything
+    // issued on `stream` so far, while the program runs levels 1..Lc
+    if (!h->side) {
+      if ((rc = hip_check(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "side stream")) ||
+          (rc = hip_check(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming), "event")) ||
+          (rc = hip_check(hipEventCreateWithFlags(&h->join, hipEventDisableTiming), "event")))
+        return rc;
+    }
+    if ((rc = hip_check(hipEventRecord(h->fork, s), "event record")) ||
+        (rc = hip_check(hipStreamWaitEvent(h->side, h->fork, 0), "stream wait")))
+      return rc;
+    for (int j = Lc + 1; j <= L; ++j)
+      if ((rc = mg_set_rhs(h, j, rhs_dev[j - 1], h->side))) return rc;
+    if ((rc = hip_check(hipEventRecord(h->join, h->side), "event record"))) return rc;
+  }
+  ExecRhs r{};
+  for (int j = 1; j <= L; ++j) r.p[j - 1] = rhs_dev[j - 1];
+  if ((rc = run_program(h, pc, s, &r))) return rc;
+  if (Lc < L && (rc = hip_check(hipStreamWaitEvent(s, h->join, 0), "stream wait"))) return rc;
+  return fmg_levels(h, Lc + 1, L, s);
 }
 
 int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out) {
@@ -925,6 +989,6 @@ int bfpk::params_ok(const mg_params* p) { return check_params(p); }
 int bfpk::set_rhs_table(mg_hierarchy* h, int level, const double* const* table_dev, int index,
                         hipStream_t s) {
   if (!h || level < 1 || level > h->prm.L) return fail(BFP_EINVAL, "bad level");
-  const int64_t shift = h->prm.ndim == 2 ? -2 * level - 2 : -2 * level - 3;
+  const int64_t shift = rhs_shift(h->prm.ndim, level);
   return from_f64_impl(nullptr, table_dev, index, shift, &h->lv[level].b, s);
 }

@@ -217,3 +217,31 @@ def test_ir_programs_match_launches(ndim, L, w, prog, policy, nu):
     b0, l0 = H0.counters()
     b1, l1 = H1.counters()
     assert abs(b0 - b1) <= 1e-9 * b0 and l1 == 5 < l0
+
+
+@pytest.mark.parametrize("ndim,L,w,prog,policy,nu,pts", [
+    (2, 8, 24, True, "nn_ir_first_q", (1, 0), 4096), (2, 5, 32, False, "q", (2, 2), 4096),
+    (3, 5, 20, True, "nn_ir_first_q", (1, 0), 4096), (2, 7, 16, True, "nn", (1, 0), 0)])
+def test_fmg_f64_matches_separate_calls(ndim, L, w, prog, policy, nu, pts):
+    """mg_fmg_f64 (coarse right-hand sides quantized inside the coarse-level
+    program, finer ones on the side stream) gives the blocks of mg_set_rhs on
+    every level followed by mg_fmg, bit for bit; twice in a row, the second
+    time with other right-hand sides (so the pointers and the fork/join order
+    are exercised)."""
+    f1 = [torch.from_numpy(np.ascontiguousarray(W.manufactured_f(j, ndim))).cuda()
+          for j in range(1, L + 1)]
+    f2 = [(-3.0 * f).contiguous() for f in f1]
+    one = _lib_hierarchy(ndim, L, w, prog, policy, nu[0], nu[1], 2, 23, pts)
+    sep = _lib_hierarchy(ndim, L, w, prog, policy, nu[0], nu[1], 2, 23, pts)
+    for rhs in (f1, f2):
+        one.fmg_f64(rhs)
+        for j in range(1, L + 1):
+            sep.set_rhs(j, rhs[j - 1])
+        sep.fmg()
+        torch.cuda.synchronize()
+        for j in range(1, L + 1):
+            for which, name in ((0, "x"), (1, "b"), (2, "r")):
+                _same_block(one.get_vec(j, which), sep.get_vec(j, which), f"{name} level {j}")
+    b1, _ = one.counters()
+    b2, _ = sep.counters()
+    assert abs(b1 - b2) <= 1e-9 * b2

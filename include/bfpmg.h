@@ -314,6 +314,32 @@ int mg_fmg(mg_hierarchy* h, void* stream);
  * events cannot be created.                                              */
 int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream);
 
+/* Diagnostics of the solves run on a hierarchy (Section 4's qcomp window,
+ * Table 2, and nnqcomp saturation, Section 6.4), kept on the device by every
+ * quantizing call the mg_* functions issue, counted per recursion level
+ * (the level of the call's input for a restriction, of its output
+ * otherwise) and call site:
+ *   sites: 0 IR residual (first iteration), 1 IR residual (later), 2 IR
+ *   correction, 3 relaxation, 4 V-cycle residual, 5 restriction, 6 V-cycle
+ *   correction, 7 FMG prolongation.
+ *   bins, MG_DIAG_BINS per (level, site):
+ *     0 .. MG_DIAG_GAP_BINS-1: qcomp calls that have an estimate gamma, by
+ *       the window gap d = mu_tmp - mu* (mu_tmp = nu(gamma) - e_z*, mu* the
+ *       exact result's leading bit): bin 0 for d < 0, bin 1 + min(d, 59).
+ *       Algorithm 1 with w_tmp = w_out + w_add recomputes exactly the calls
+ *       with d < 0 (overflow) or d > w_add (underflow);
+ *     61: nnqcomp calls; 62: entries they saturated; 63: nnqcomp calls that
+ *       saturated at least one entry.
+ * mg_diag_read synchronizes `stream`, copies the counters to host_out
+ * (int64, [MG_MAX_LEVELS + 1][MG_DIAG_SITES][MG_DIAG_BINS], row 0 unused)
+ * and, when reset != 0, zeroes them. Counters start at zero when the
+ * hierarchy is created. BFP_EINVAL for a NULL argument. Work that is still
+ * running on other streams is not waited for.                            */
+#define MG_DIAG_SITES 8
+#define MG_DIAG_BINS 64
+#define MG_DIAG_GAP_BINS 61
+int mg_diag_read(mg_hierarchy* h, int64_t* host_out, int reset, void* stream);
+
 /* `iters` IR-V(nu1,nu2) iterations on level `level` from its current x.   */
 int mg_ir(mg_hierarchy* h, int level, int iters, void* stream);
 

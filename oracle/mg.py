@@ -29,6 +29,17 @@ Readings where the paper is silent or the configurations ask for more:
     with w the finest inner width, A and b at 32 bits.
   * c1, c2 floor-quantized to 16 bits; rho = 2 (the Gershgorin bound for
     diag-scaled 5- and 7-point operators, valid on every level).
+
+Diagnostics (Section 4's window and Table 2; Section 6.4's saturation): per
+recursion level (the input's level for a restriction, the output's
+otherwise) and call site, 64 counters. A qcomp call with an estimate gamma
+counts its window gap d = mu_tmp - mu*, mu_tmp = nu(gamma) - e_z* the top
+of the window the estimate gives and mu* the exact result's leading bit:
+bin 0 for d < 0, bin 1 + min(d, 59) otherwise. Algorithm 1 with
+w_tmp = w_out + w_add recomputes exactly when d < 0 (overflow) or
+d > w_add (underflow), so one histogram answers every w_add of a Table 2
+sweep. An nnqcomp call counts in bin 61, its saturated entries in bin 62,
+and in bin 63 if it saturated any.
 """
 from __future__ import annotations
 
@@ -39,11 +50,29 @@ from typing import Callable
 import numpy as np
 
 from . import blas
-from .bfp import BFP, Scalar, as_block, quantize, scalar_from_fraction
+from .bfp import BFP, Scalar, as_block, nu, quantize, scalar_from_fraction
 from .fd import Stencil, prolongation, rhs_log2_scale, scaled_A, scaled_R
 
 ONE = Scalar(1, 0, 2)
 MINUS_ONE = Scalar(-1, 0, 1)
+
+# call sites, in the order of the diagnostics rows
+SITES = ("ir_res_first", "ir_res", "ir_corr", "relax", "v_res", "restrict", "v_corr",
+         "fmg_prol")
+DIAG_BINS, DIAG_GAP_BINS = 64, 61
+DIAG_NN_CALLS, DIAG_NN_SAT, DIAG_NN_SAT_CALLS = 61, 62, 63
+
+
+def gap_bin(d: int) -> int:
+    """Diagnostics bin of a qcomp window gap d = mu_tmp - mu*."""
+    return 0 if d < 0 else 1 + min(d, DIAG_GAP_BINS - 2)
+
+
+def recomputations(row, w_add: int) -> int:
+    """Calls of a diagnostics row that Algorithm 1 with w_tmp = w_out + w_add
+    recomputes: overflow (d < 0) or underflow (d > w_add)."""
+    return int(row[0]) + sum(int(row[1 + d]) for d in range(w_add + 1, DIAG_GAP_BINS - 1))
+
 
 # Table 1: extra window bits w_add per call site (used by qcomp's window).
 W_ADD = {
@@ -135,6 +164,20 @@ class Stats:
     recomputations: int = 0
     saturations: int = 0
     per_site: dict = field(default_factory=dict)
+    diag: dict = field(default_factory=dict)     # (level, site index) -> 64 counters
+
+    def diag_row(self, level: int, site: str) -> list:
+        key = (level, SITES.index(site))
+        if key not in self.diag:
+            self.diag[key] = [0] * DIAG_BINS
+        return self.diag[key]
+
+    def diag_array(self, max_level: int = 16) -> np.ndarray:
+        """The counters as [level 0..max_level][site][bin] (row 0 unused)."""
+        a = np.zeros((max_level + 1, len(SITES), DIAG_BINS), dtype=np.int64)
+        for (level, k), row in self.diag.items():
+            a[level, k] = row
+        return a
 
     def add(self, site: str, info: blas.QInfo) -> None:
         self.calls += 1
@@ -213,6 +256,16 @@ def _quantize_op(H: Hierarchy, site: str, op: blas.Exact, w_out: int,
     else:
         out, info = blas.nnqcomp(op, w_out, gamma)
     H.stats.add(site, info)
+    # diagnostics, on the recursion level of the call
+    j = (out.m.shape[0] - 1).bit_length() - 1
+    row = H.stats.diag_row(j + 1 if site == "restrict" else j, site)
+    if use_q:
+        if gamma is not None and gamma > 0:
+            row[gap_bin(nu(Fraction(gamma)) - op.e - info.mu_star)] += 1
+    else:
+        row[DIAG_NN_CALLS] += 1
+        row[DIAG_NN_SAT] += info.saturated
+        row[DIAG_NN_SAT_CALLS] += int(info.saturated > 0)
     return out
 
 

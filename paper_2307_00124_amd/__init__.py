@@ -340,6 +340,15 @@ class Hierarchy:
     def fmg(self, stream=None) -> None:
         check(lib.mg_fmg(self.h, _stream(stream)), "mg_fmg")
 
+    def diagnostics(self, reset: bool = False, stream=None):
+        """mg_diag_read: the solve diagnostics as an int64 numpy array
+        [level 0..MG_MAX_LEVELS][site][bin] (synchronizes `stream`)."""
+        import numpy as np
+        out = np.zeros((abi.MG_MAX_LEVELS + 1, abi.MG_DIAG_SITES, abi.MG_DIAG_BINS), dtype=np.int64)
+        check(lib.mg_diag_read(self.h, out.ctypes.data_as(C.c_void_p), int(reset), _stream(stream)),
+              "mg_diag_read")
+        return out
+
     def ir(self, level: int, iters: int, stream=None) -> None:
         check(lib.mg_ir(self.h, level, iters, _stream(stream)), "mg_ir")
 

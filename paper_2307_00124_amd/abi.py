@@ -19,6 +19,9 @@ BFP_NORMALIZE, BFP_SATURATE = 0, 1
 BFP_STENCIL_A, BFP_STENCIL_R, BFP_STENCIL_P = 0, 1, 2
 BFP_GAMMA_NORM, BFP_GAMMA_SUM, BFP_GAMMA_EXPLICIT = 1, 2, 3
 BFP_META_SLOTS = 288
+MG_DIAG_SITES = 8
+MG_DIAG_BINS = 64
+MG_DIAG_GAP_BINS = 61
 BFP_META_EXP, BFP_META_MAX, BFP_META_MIN, BFP_META_SAT, BFP_META_MU, BFP_META_FLAGS = range(6)
 MG_POLICY_Q, MG_POLICY_NN, MG_POLICY_NN_IR_FIRST_Q, MG_POLICY_NN_IR_FIRST2_Q, MG_POLICY_NN_IR_Q = range(5)
 MG_MAX_LEVELS = 16
@@ -101,6 +104,7 @@ SIGNATURES = {
     "mg_set_x": (I, [VP, I, VP, VP]),
     "mg_fmg": (I, [VP, VP]),
     "mg_fmg_f64": (I, [VP, VP, VP]),
+    "mg_diag_read": (I, [VP, VP, I, VP]),
     "mg_ir": (I, [VP, I, I, VP]),
     "mg_vcycle": (I, [VP, I, P(bfp_vec), P(bfp_vec), VP]),
     "mg_get_vec": (I, [VP, I, I, P(bfp_vec)]),

@@ -39,6 +39,12 @@ static thread_local std::vector<ExecOp>* g_rec = nullptr;
 void record_into(std::vector<ExecOp>* sink) { g_rec = sink; }
 bool recording() { return g_rec != nullptr; }
 
+// While set (on this host thread), the operations count their diagnostics
+// into these kDiagBins counters (and carry their estimate in qcomp mode).
+static thread_local int64_t* g_diag = nullptr;
+
+void set_diag_row(int64_t* row) { g_diag = row; }
+
 static int64_t out_n(const StarLaunch& l) { return l.n; }
 static int64_t out_n(const TransferLaunch& l) { return l.n_out; }
 static int64_t out_n(const PointLaunch& l) { return l.n; }
@@ -155,7 +161,9 @@ static int check_scalar(const bfp_scalar* s, const char* name, int max_bits) {
 
 int fill_gamma(const bfp_gamma* g, int mode, GammaArgs* out) {
   std::memset(out, 0, sizeof *out);
-  if (mode != BFP_SATURATE) return BFP_OK;
+  // qcomp needs no estimate; with diagnostics on it carries the one given,
+  // for the window-gap count
+  if (mode != BFP_SATURATE && !(g && g_diag)) return BFP_OK;
   if (!g) return fail(BFP_EINVAL, "BFP_SATURATE needs a gamma estimate");
   out->rule = g->rule;
   out->a = g->a_meta;
@@ -240,6 +248,7 @@ static void fill_common(OpArgs* op, int w_out, const bfp_vec* x, const bfp_vec* 
   op->has_y = y != nullptr;
   op->lo = -((int64_t)1 << (w_out - 1));
   op->hi = ((int64_t)1 << (w_out - 1)) - 1;
+  op->diag = g_diag;
 }
 
 // Run one op in the requested mode: nnqcomp in one launch, qcomp as the

@@ -34,6 +34,9 @@ int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta
 // ExecOps to it instead of launching kernels.
 void record_into(std::vector<ExecOp>* sink);
 bool recording();
+// Diagnostic counters (kDiagBins) that the next operations issued on this
+// host thread count into; null turns the counting off.
+void set_diag_row(int64_t* row);
 // grids of at most this many points run inside recorded programs (0: never)
 int exec_max_points();
 // Give every op of a recorded program the slots of its metadata blocks in

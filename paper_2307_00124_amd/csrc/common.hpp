@@ -23,6 +23,19 @@ constexpr int kMetaSlots = kSetBase + kSets * kSetStride;           // 288
 
 constexpr int kGammaNorm = 1, kGammaSum = 2, kGammaExplicit = 3;
 
+// Diagnostics of one (level, call site) of a solve: 64 counters.
+//   bins 0..60: qcomp calls with an estimate, by the window gap
+//     d = mu_tmp - mu* (mu_tmp = nu(gamma) - e_z*, the top of the window the
+//     estimate gives; Algorithm 1 recomputes when d < 0 — overflow — or when
+//     d > w_tmp - w_out — underflow): bin 0 for d < 0, bin 1 + min(d, 59);
+//   bin 61: nnqcomp calls; bin 62: entries they saturated; bin 63: nnqcomp
+//   calls that saturated at least one entry.
+constexpr int kDiagBins = 64, kDiagGapBins = 61, kDiagNnCalls = 61, kDiagNnSat = 62,
+              kDiagNnSatCalls = 63;
+__host__ __device__ inline int diag_gap_bin(int64_t d) {
+  return d < 0 ? 0 : 1 + (int)(d < kDiagGapBins - 2 ? d : kDiagGapBins - 2);
+}
+
 // kModeSat: nnqcomp; kModeQ1 / kModeQ2: the two passes of qcomp;
 // kModeNormMeta: qcomp of a stored block whose mu* is known from its metadata;
 // kModeAssign: keep the mantissas, set the exponent, recompute the metadata
@@ -50,6 +63,7 @@ struct OpArgs {
   int64_t lo, hi;           // X_w_out
   int64_t assign_exp;       // kModeAssign only
   int abits, bbits;         // |alpha S x| < 2^abits and |beta y| < 2^bbits
+  int64_t* diag;            // kDiagBins diagnostic counters of the op's call site, or null
 };
 
 // A padded, row-pitched grid: rows = (n+2)^(ndim-1) rows of `pitch` elements.

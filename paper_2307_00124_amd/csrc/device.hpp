@@ -250,10 +250,27 @@ __device__ __forceinline__ int64_t block_max(int64_t v, int64_t* red) {
   return b;
 }
 
+// Diagnostic counts of a finished op (no-return atomics: nothing waits on
+// them before the launch ends).
+__device__ __forceinline__ void diag_count(int64_t* diag, int dbin, int dsat, int64_t nsat) {
+  if (!diag) return;
+  if (dbin >= 0) atomicAdd((unsigned long long*)&diag[dbin], 1ull);
+  if (dsat) {
+    atomicAdd((unsigned long long*)&diag[kDiagNnCalls], 1ull);
+    if (nsat) {
+      atomicAdd((unsigned long long*)&diag[kDiagNnSat], (unsigned long long)nsat);
+      atomicAdd((unsigned long long*)&diag[kDiagNnSatCalls], 1ull);
+    }
+  }
+}
+
 // Reduce the per-thread (max, min, saturations) of a block's outputs; the
-// last block publishes exponent / max / min / saturation count.
+// last block publishes exponent / max / min / saturation count (and the
+// op's diagnostic counts when `diag` is set).
 __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64_t tsat,
-                                               int64_t* zm, int64_t e_out) {
+                                               int64_t* zm, int64_t e_out,
+                                               int64_t* diag = nullptr, int dbin = -1,
+                                               int dsat = 0) {
   __shared__ int64_t s_red[3][kBlock / 64];
   const int tid = threadIdx.x;
   tmax = wave_max(tmax);
@@ -277,6 +294,7 @@ __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64
       zm[kMetaMin] = bmin;
       zm[kMetaSat] = bsat;
       zm[kMetaExp] = e_out;
+      diag_count(diag, dbin, dsat, bsat);
       return;
     }
     int64_t* set = acc_set(zm);
@@ -297,6 +315,7 @@ __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64
       zm[kMetaMin] = mn;
       zm[kMetaSat] = st;
       zm[kMetaExp] = e_out;
+      diag_count(diag, dbin, dsat, st);
     }
   }
 }
@@ -336,15 +355,15 @@ struct Resolved {
   int64_t sa;    // single-term shift when there is no y
 };
 
+// nu / zero: gamma_nu of the op's estimate (used in saturate mode)
 template <class MA>
-__device__ __forceinline__ Resolved resolve(const OpArgs& p, const MA& ma) {
+__device__ __forceinline__ Resolved resolve_nu(const OpArgs& p, const MA& ma, int64_t nu,
+                                               bool zero) {
   Resolved r;
   r.ea = p.alpha_e + p.e_A + ma(kOpX, kMetaExp);
   r.eb = p.has_y ? p.beta_e + ma(kOpY, kMetaExp) : r.ea;
   r.ez = r.ea < r.eb ? r.ea : r.eb;
   if (p.mode == kModeSat) {
-    bool zero;
-    int64_t nu = gamma_nu(p.g, ma, &zero);
     r.eo = zero ? r.ez + 1 - p.w_out : nu - p.w_out;
   } else if (p.mode == kModeQ2) {
     r.eo = r.ez + ma(kOpZ, kMetaMu) - p.w_out;
@@ -360,6 +379,13 @@ __device__ __forceinline__ Resolved resolve(const OpArgs& p, const MA& ma) {
   r.sa = p.mode == kModeAssign ? 0 : r.ea - r.eo;
   r.cmb = make_combine(r.ea - r.eo, r.eb - r.eo);
   return r;
+}
+
+template <class MA>
+__device__ __forceinline__ Resolved resolve(const OpArgs& p, const MA& ma) {
+  bool zero = true;
+  const int64_t nu = p.mode == kModeSat ? gamma_nu(p.g, ma, &zero) : 0;
+  return resolve_nu(p, ma, nu, zero);
 }
 
 __device__ __forceinline__ PtrMeta ptr_meta(const OpArgs& p) {

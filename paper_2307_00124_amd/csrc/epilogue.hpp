@@ -125,12 +125,20 @@ struct Epi {
   int32_t tmax, tmin;
   int64_t tmu;
   int64_t* zm;
+  int64_t* diag;   // the call site's diagnostic counters (or null)
+  int dbin;        // qcomp window-gap bin to count, or -1
+  int dsat;        // 1: count an nnqcomp call and its saturations
 
   __device__ __forceinline__ void init(const OpArgs& op) { init(op, ptr_meta(op)); }
 
   template <class MA>
   __device__ __forceinline__ void init(const OpArgs& op, const MA& ma) {
-    R = resolve(op, ma);
+    // gamma_nu once: the saturate mode's output exponent, and the window
+    // gap a diagnosed qcomp call counts
+    const bool gap = op.diag && op.mode == kModeQ2;
+    bool zero = true;
+    const int64_t nu = (op.mode == kModeSat || gap) ? gamma_nu(op.g, ma, &zero) : 0;
+    R = resolve_nu(op, ma, nu, zero);
     alpha_m = op.alpha_m;
     beta_m = op.beta_m;
     lo = op.lo;
@@ -175,6 +183,12 @@ struct Epi {
     tmin = 0;
     tsat = 0;
     tmu = 1;
+    // diagnostics: the window gap of a qcomp call with an estimate (the
+    // second pass knows mu* = eo - ez + w_out), or an nnqcomp call
+    diag = op.diag;
+    // mu* = eo - ez + w_out in the second qcomp pass
+    dbin = gap && !zero ? diag_gap_bin(nu - R.ez - (R.eo - R.ez + op.w_out)) : -1;
+    dsat = diag && op.mode == kModeSat;
   }
 
   __device__ __forceinline__ int64_t mul_a(int64_t g) const { return alpha_m * g; }
@@ -225,7 +239,7 @@ struct Epi {
 
   __device__ __forceinline__ void finish() {
     if (PASS == kQ1) finish_mu(tmu, zm);
-    else finish_outputs(tmax, tmin, tsat, zm, R.eo);
+    else finish_outputs(tmax, tmin, tsat, zm, R.eo, diag, dbin, dsat);
   }
 };
 

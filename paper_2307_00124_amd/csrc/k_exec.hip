@@ -65,15 +65,18 @@ __device__ __forceinline__ void stv(void* p, int bits, int64_t i, int64_t v) {
 typedef int64_t MetaRow[kExMetaF];
 
 // Operand metadata read from the LDS mirror by slot.
+struct PendingDiag;
 struct LdsMeta {
   MetaRow* lm;
+  PendingDiag* pend;   // where the op leaves its diagnostic counts
   int s[5];
   __device__ __forceinline__ int64_t operator()(int k, int f) const { return lm[s[k]][f]; }
 };
 
-__device__ __forceinline__ LdsMeta lds_meta(MetaRow* lm, const int16_t* slot) {
+__device__ __forceinline__ LdsMeta lds_meta(MetaRow* lm, PendingDiag* pend, const int16_t* slot) {
   LdsMeta m;
   m.lm = lm;
+  m.pend = pend;
   m.s[kOpX] = slot[0];
   m.s[kOpY] = slot[1] >= 0 ? slot[1] : slot[0];
   m.s[kOpZ] = slot[2];
@@ -90,8 +93,18 @@ struct Red {
   int32_t v[3][kWaves];
 };
 
+// An op's diagnostic counts, left by its reduction for thread 0 to issue
+// at the start of the next op (then nothing on the op's own path waits for
+// the atomics' acknowledgement).
+struct PendingDiag {
+  int64_t* diag;
+  int dbin, dsat;
+  int64_t nsat;
+};
+
 template <int NT, int PASS, bool HASY>
-__device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm) {
+__device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm,
+                                          PendingDiag& pend) {
   constexpr int kExWaves = NT / 64;
   __shared__ Red<NT> R;
   auto& red = R.v;
@@ -122,6 +135,7 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm)
         zm[kMetaMin] = mn;
         zm[kMetaSat] = st;
         zm[kMetaExp] = E.R.eo;
+        if (E.diag) pend = PendingDiag{E.diag, E.dbin, E.dsat, st};
       }
     }
   }
@@ -179,7 +193,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   // the fast epilogue when no intermediate can overflow (decided once per op)
   if (PASS != kQ1 && E.fast) body(std::integral_constant<int, kVarFast>());
   else body(std::integral_constant<int, kVarGen>());
-  ex_finish<NT>(E, ma.lm[ma.s[kOpZ]]);
+  ex_finish<NT>(E, ma.lm[ma.s[kOpZ]], *ma.pend);
 }
 
 template <int NT, int ND, int PASS, bool HASY>
@@ -304,9 +318,9 @@ __device__ __forceinline__ OpArgs with_mode(const OpArgs& a, int mode) {
 }
 
 template <int NT, int ND, int PASS, bool HASY>
-__device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, int mode,
-                                            uintptr_t base) {
-  const LdsMeta ma = lds_meta(lm, op.slot);
+__device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, PendingDiag* pend,
+                                            int mode, uintptr_t base) {
+  const LdsMeta ma = lds_meta(lm, pend, op.slot);
   if (op.kind == kExStar) {
     ex_star<NT, ND, PASS, HASY>(op.u.star, with_mode(op.u.star.op, mode), ma, base);
   } else if (op.kind == kExPoint) {
@@ -424,7 +438,9 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
                                             uintptr_t base, const double* const* rhs) {
   __shared__ MetaRow lm[kExecMaxMeta];
   __shared__ ExecOp buf[2];
+  __shared__ PendingDiag pend;
   const int t = threadIdx.x;
+  if (t == 0) pend.diag = nullptr;
   const uint32_t* gw = reinterpret_cast<const uint32_t*>(ops);
   uint32_t* bw = reinterpret_cast<uint32_t*>(buf);
   for (int i = t; i < nmeta * kExMetaF; i += NT)
@@ -436,6 +452,10 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
     const bool pre = t < kOpWords && k + 1 < count;
     const uint32_t nextw = pre ? gw[(int64_t)(k + 1) * kOpWords + t] : 0;
     const ExecOp& op = buf[k & 1];
+    if (t == 0 && pend.diag) {   // the previous op's diagnostic counts
+      diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);
+      pend.diag = nullptr;
+    }
     if (op.kind == kExZero) {
       ex_zero<NT>(op.u.zero, lm[op.slot[2]], base);
     } else if (op.kind == kExConv) {
@@ -446,16 +466,16 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
                                                                  : op.u.tr.op.has_y);
       if (op.mode == kExModeQ) {
         if (hasy) {
-          ex_dispatch<NT, ND, kQ1, true>(op, lm, kModeQ1, base);
-          ex_dispatch<NT, ND, kOut, true>(op, lm, kModeQ2, base);
+          ex_dispatch<NT, ND, kQ1, true>(op, lm, &pend, kModeQ1, base);
+          ex_dispatch<NT, ND, kOut, true>(op, lm, &pend, kModeQ2, base);
         } else {
-          ex_dispatch<NT, ND, kQ1, false>(op, lm, kModeQ1, base);
-          ex_dispatch<NT, ND, kOut, false>(op, lm, kModeQ2, base);
+          ex_dispatch<NT, ND, kQ1, false>(op, lm, &pend, kModeQ1, base);
+          ex_dispatch<NT, ND, kOut, false>(op, lm, &pend, kModeQ2, base);
         }
       } else if (hasy) {
-        ex_dispatch<NT, ND, kOut, true>(op, lm, op.mode, base);
+        ex_dispatch<NT, ND, kOut, true>(op, lm, &pend, op.mode, base);
       } else {
-        ex_dispatch<NT, ND, kOut, false>(op, lm, op.mode, base);
+        ex_dispatch<NT, ND, kOut, false>(op, lm, &pend, op.mode, base);
       }
     }
     if (pre) bw[((k + 1) & 1) * kOpWords + t] = nextw;
@@ -463,6 +483,7 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
   }
   for (int i = t; i < nmeta * kExMetaF; i += NT)
     ((BFP_GLOBAL int64_t*)rel(metas[i / kExMetaF], base))[i % kExMetaF] = lm[i / kExMetaF][i % kExMetaF];
+  if (t == 0 && pend.diag) diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);
 }
 
 template <int ND>

@@ -29,7 +29,12 @@ using namespace bfpk;
 
 namespace {
 
-enum Site { kIrResFirst, kIrRes, kIrCorr, kRelax, kVRes, kRestrict, kVCorr, kFmgProl };
+// call sites of the quantizing operations (the rows of the diagnostics)
+enum Site { kIrResFirst, kIrRes, kIrCorr, kRelax, kVRes, kRestrict, kVCorr, kFmgProl, kDiagSites };
+constexpr size_t kDiagBytes = (size_t)(MG_MAX_LEVELS + 1) * kDiagSites * kDiagBins * sizeof(int64_t);
+static_assert(kDiagSites == MG_DIAG_SITES && kDiagBins == MG_DIAG_BINS &&
+                  kDiagGapBins == MG_DIAG_GAP_BINS,
+              "header diagnostics layout");
 
 struct Level {
   int j;
@@ -66,6 +71,9 @@ struct mg_hierarchy {
   // (the first, the second, any later one), and FMG on levels 1..Lc that
   // first quantizes those levels' right-hand sides from FP64
   Program prog[kPrograms];
+  // diagnostic counters [level 0..MG_MAX_LEVELS][site][kDiagBins] in the
+  // arena (null for hierarchies that keep none, e.g. the batched ones)
+  int64_t* diag = nullptr;
   // mg_fmg_f64: a second stream (created on first use) that quantizes the
   // finer levels' right-hand sides while the program runs the coarse ones
   hipStream_t side = nullptr;
@@ -170,9 +178,26 @@ int mode_for(const mg_hierarchy* h, Site site, bool plain_first2) {
 
 // --------------------------------------------------------------- ops ----
 
+// The diagnostic counters of a call site on the level the call belongs to
+// (the recursion level: the input's for a restriction, the output's
+// otherwise), while the call is issued; null when the hierarchy keeps none.
+int level_of(int64_t n) {
+  int j = 0;
+  while (((int64_t)1 << j) - 1 < n) ++j;
+  return j;
+}
+struct DiagScope {
+  DiagScope(mg_hierarchy* h, Site site, int64_t n) {
+    set_diag_row(h->diag ? h->diag + ((int64_t)level_of(n) * kDiagSites + site) * kDiagBins
+                         : nullptr);
+  }
+  ~DiagScope() { set_diag_row(nullptr); }
+};
+
 int op_stencil(mg_hierarchy* h, const bfp_stencil* S, const bfp_vec& x, const bfp_scalar* al,
-               const bfp_scalar* be, const bfp_vec* y, bfp_vec& z, int mode, const bfp_gamma& g,
-               hipStream_t s) {
+               const bfp_scalar* be, const bfp_vec* y, bfp_vec& z, Site site, int mode,
+               const bfp_gamma& g, hipStream_t s) {
+  DiagScope diag(h, site, site == kRestrict ? x.n : z.n);
   int rc = stencil_apply_impl(S, &x, al, be, y, z.w, mode, &g, &z, s, 0);
   if (rc) return rc;
   const int passes = mode == BFP_NORMALIZE ? 2 : 1;
@@ -182,8 +207,9 @@ int op_stencil(mg_hierarchy* h, const bfp_stencil* S, const bfp_vec& x, const bf
   return BFP_OK;
 }
 
-int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, int mode,
+int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, Site site, int mode,
            const bfp_gamma& g, hipStream_t s) {
+  DiagScope diag(h, site, z.n);
   int rc = point_impl(&kOne, &x, &kMinusOne, &y, z.w, mode, &g, &z, s, -1);
   if (rc) return rc;
   const int passes = mode == BFP_NORMALIZE ? 2 : 1;
@@ -211,44 +237,44 @@ int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
       rin.meta == L.vr.meta)
     return run_program(h, h->prog[kPV], s);
   // relaxation from y = 0: y = c2 A r + c1 r
-  if ((rc = op_stencil(h, &h->A, rin, &p.c2, &p.c1, &rin, L.y, mode_for(h, kRelax, false),
+  if ((rc = op_stencil(h, &h->A, rin, &p.c2, &p.c1, &rin, L.y, kRelax, mode_for(h, kRelax, false),
                        g_norm(rin, p.c1), s)))
     return rc;
   const bfp_vec* last = nullptr;
   for (int k = 1; k < p.nu1; ++k) {
     if ((rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
-                         mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
+                         kVRes, mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
       return rc;
-    if ((rc = op_stencil(h, &h->A, L.s, &p.c2, &p.c1, &L.s, L.t, mode_for(h, kRelax, false),
+    if ((rc = op_stencil(h, &h->A, L.s, &p.c2, &p.c1, &L.s, L.t, kRelax, mode_for(h, kRelax, false),
                          g_norm(L.s, p.c1), s)))
       return rc;
-    if ((rc = op_sub(h, L.y, L.t, L.y, mode_for(h, kVCorr, false), g_sum(L.y, L.t), s)))
+    if ((rc = op_sub(h, L.y, L.t, L.y, kVCorr, mode_for(h, kVCorr, false), g_sum(L.y, L.t), s)))
       return rc;
     last = &L.s;
   }
   if (l > 1) {
     Level& C = h->lv[l - 1];
     if ((rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
-                         mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
+                         kVRes, mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
       return rc;
     if ((rc = op_stencil(h, &h->R, L.s, &kOne, nullptr, nullptr, C.vr,
-                         mode_for(h, kRestrict, false), g_norm(L.s, kFour), s)))
+                         kRestrict, mode_for(h, kRestrict, false), g_norm(L.s, kFour), s)))
       return rc;
     if ((rc = vcycle(h, l - 1, C.vr, s))) return rc;
     if ((rc = op_stencil(h, &h->P, C.y, &kMinusOne, &kOne, &L.y, L.y,
-                         mode_for(h, kVCorr, false), g_sum(L.y, C.y), s)))
+                         kVCorr, mode_for(h, kVCorr, false), g_sum(L.y, C.y), s)))
       return rc;
     last = &L.s;
   }
   for (int k = 0; k < p.nu2; ++k) {
     bfp_gamma g = last ? g_norm(*last, kOne) : g_norm(rin, h->vres);
     if ((rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
-                         mode_for(h, kVRes, false), g, s)))
+                         kVRes, mode_for(h, kVRes, false), g, s)))
       return rc;
-    if ((rc = op_stencil(h, &h->A, L.s, &p.c2, &p.c1, &L.s, L.t, mode_for(h, kRelax, false),
+    if ((rc = op_stencil(h, &h->A, L.s, &p.c2, &p.c1, &L.s, L.t, kRelax, mode_for(h, kRelax, false),
                          g_norm(L.s, p.c1), s)))
       return rc;
-    if ((rc = op_sub(h, L.y, L.t, L.y, mode_for(h, kVCorr, false), g_sum(L.y, L.t), s)))
+    if ((rc = op_sub(h, L.y, L.t, L.y, kVCorr, mode_for(h, kVCorr, false), g_sum(L.y, L.t), s)))
       return rc;
     last = &L.s;
   }
@@ -260,15 +286,16 @@ int ir_iteration(mg_hierarchy* h, int l, const bfp_gamma* gres, bool first, bool
                  hipStream_t s) {
   Level& L = h->lv[l];
   int rc;
-  int mode = mode_for(h, first ? kIrResFirst : kIrRes, plain_first2);
+  const Site site = first ? kIrResFirst : kIrRes;
+  int mode = mode_for(h, site, plain_first2);
   if (!gres) mode = BFP_NORMALIZE;   // no estimate exists: qcomp
   bfp_gamma gdummy{};
   gdummy.rule = BFP_GAMMA_EXPLICIT;
-  if ((rc = op_stencil(h, &h->A, L.x, &kOne, &kMinusOne, &L.b, L.r, mode,
+  if ((rc = op_stencil(h, &h->A, L.x, &kOne, &kMinusOne, &L.b, L.r, site, mode,
                        gres ? *gres : gdummy, s)))
     return rc;
   if ((rc = vcycle(h, l, L.r, s))) return rc;
-  return op_sub(h, L.x, L.y, L.x, mode_for(h, kIrCorr, false), g_sum(L.x, L.y), s);
+  return op_sub(h, L.x, L.y, L.x, kIrCorr, mode_for(h, kIrCorr, false), g_sum(L.x, L.y), s);
 }
 
 // FMG levels lo..hi (lo = 1 starts from x_1 = 0)
@@ -284,7 +311,7 @@ int fmg_levels(mg_hierarchy* h, int lo, int hi, hipStream_t s) {
     if (l > 1) {
       Level& C = h->lv[l - 1];
       if ((rc = op_stencil(h, &h->P, C.x, &kOne, nullptr, nullptr, L.x,
-                           mode_for(h, kFmgProl, false), g_norm(C.x, kOne), s)))
+                           kFmgProl, mode_for(h, kFmgProl, false), g_norm(C.x, kOne), s)))
         return rc;
     }
     for (int i = 1; i <= p.N; ++i) {
@@ -382,7 +409,8 @@ int check_params(const mg_params* p) {
 
 // Lay out (or only size) every level's blocks in the arena, followed by
 // room for `nops` recorded operations.
-size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops) {
+// diag: also reserve the diagnostic counters (h->diag) after the programs
+size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops, bool diag) {
   size_t off = 0;
   const int mb = p->min_storage_bits;
   for (int j = 1; j <= p->L; ++j) {
@@ -413,6 +441,11 @@ size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops) {
   off = align256(off + kPrograms * kExecMaxMeta * sizeof(int64_t*));
   h->prog[0].ops = base ? (ExecOp*)(base + off) : nullptr;
   off = align256(off + nops * sizeof(ExecOp));
+  h->diag = nullptr;
+  if (diag) {
+    h->diag = base ? (int64_t*)(base + off) : nullptr;
+    off = align256(off + kDiagBytes);
+  }
   return off;
 }
 
@@ -444,7 +477,7 @@ int count_ops(const mg_params* prm, int64_t exec_points, size_t* nops) {
   if (!h) return fail(BFP_ENOMEM, "host allocation failed");
   int rc = setup(h, prm, exec_points);
   if (!rc) {
-    layout(h, prm, reinterpret_cast<char*>((uintptr_t)1 << 20), 0);
+    layout(h, prm, reinterpret_cast<char*>((uintptr_t)1 << 20), 0, false);
     std::vector<ExecOp> Pg[kPrograms];
     double bytes[kPrograms];
     rc = record_programs(h, Pg, bytes);
@@ -503,6 +536,11 @@ int record_batch_program(BatchGroup& g) {
   if (rc) return rc;
   if ((rc = exec_assign_slots(g.ops, g.metas))) return rc;
   for (ExecOp& e : g.ops) {
+    // relocatable programs keep no diagnostics (their pointers would not move)
+    const OpArgs* a = e.kind == kExStar ? &e.u.star.op
+                      : e.kind == kExTransfer ? &e.u.tr.op
+                      : e.kind == kExPoint ? &e.u.pt.op : nullptr;
+    if (a && a->diag) return fail(BFP_EINVAL, "batched program with diagnostics");
     switch (e.kind) {
       case kExStar: unbase(e.u.star.x); unbase(e.u.star.y); unbase(e.u.star.z); break;
       case kExTransfer: unbase(e.u.tr.x); unbase(e.u.tr.y); unbase(e.u.tr.z); break;
@@ -561,7 +599,7 @@ int plan_batch(mg_batch* B, const mg_params* prms, int nprob, char* arena, size_
       BatchGroup& G = B->groups.back();
       if ((rc = setup(G.h, &G.prm, 0))) return rc;
       G.h->Lc = 0;
-      G.region = layout(G.h, &G.prm, reinterpret_cast<char*>(kStandIn), 0);
+      G.region = layout(G.h, &G.prm, reinterpret_cast<char*>(kStandIn), 0, false);
       if ((rc = record_batch_program(G))) return rc;
     }
     B->group_of[i] = gi;
@@ -690,7 +728,7 @@ int bfpk::hierarchy_bytes_ex(const mg_params* prm, int64_t exec_points, size_t* 
   size_t nops = 0;
   if ((rc = count_ops(prm, exec_points, &nops))) return rc;
   mg_hierarchy tmp;
-  *bytes = layout(&tmp, prm, nullptr, nops);
+  *bytes = layout(&tmp, prm, nullptr, nops, true);
   return BFP_OK;
 }
 
@@ -705,18 +743,22 @@ int bfpk::hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t byte
   mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
   if (!h) return fail(BFP_ENOMEM, "host allocation failed");
   if ((rc = setup(h, prm, exec_points))) { delete h; return rc; }
-  const size_t need = layout(h, prm, nullptr, nops);
+  const size_t need = layout(h, prm, nullptr, nops, true);
   if (bytes < need) {
     delete h;
     return fail(BFP_ENOMEM, "arena holds %zu bytes, the hierarchy needs %zu", bytes, need);
   }
-  layout(h, prm, static_cast<char*>(arena_dev), nops);
+  layout(h, prm, static_cast<char*>(arena_dev), nops, true);
   hipStream_t s = (hipStream_t)stream;
   for (int j = 1; j <= prm->L; ++j) {
     Level& L = h->lv[j];
     for (bfp_vec* v : {&L.x, &L.b, &L.r, &L.vr, &L.y, &L.s, &L.t}) {
       if ((rc = bfp_vec_init(v, stream))) { delete h; return rc; }
     }
+  }
+  if ((rc = hip_check(hipMemsetAsync(h->diag, 0, kDiagBytes, s), "diagnostics reset"))) {
+    delete h;
+    return rc;
   }
   std::vector<ExecOp> Pg[kPrograms];
   std::vector<int64_t*> M[kPrograms];
@@ -847,6 +889,20 @@ int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream) {
   if ((rc = run_program(h, pc, s, &r))) return rc;
   if (Lc < L && (rc = hip_check(hipStreamWaitEvent(s, h->join, 0), "stream wait"))) return rc;
   return fmg_levels(h, Lc + 1, L, s);
+}
+
+int mg_diag_read(mg_hierarchy* h, int64_t* host_out, int reset, void* stream) {
+  if (!h || !host_out) return fail(BFP_EINVAL, "NULL argument");
+  if (!h->diag) return fail(BFP_EINVAL, "this hierarchy keeps no diagnostics");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = hip_check(hipStreamSynchronize(s), "diagnostics read");
+  if (!rc) rc = hip_check(hipMemcpy(host_out, h->diag, kDiagBytes, hipMemcpyDeviceToHost),
+                          "diagnostics read");
+  if (!rc && reset) {
+    rc = hip_check(hipMemsetAsync(h->diag, 0, kDiagBytes, s), "diagnostics reset");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "diagnostics reset");
+  }
+  return rc;
 }
 
 int mg_get_vec(mg_hierarchy* h, int level, int which, bfp_vec* out) {

@@ -32,6 +32,15 @@ def test_every_declared_function_is_exported_and_bound():
         assert n in abi.SIGNATURES, f"{n} has no ctypes signature"
 
 
+def test_header_constants_match_the_binding_and_the_oracle():
+    text = open(HEADER).read()
+    macros = dict(re.findall(r"^#define\s+(\w+)\s+(\d+)\s*$", text, flags=re.M))
+    for name in ("MG_MAX_LEVELS", "MG_DIAG_SITES", "MG_DIAG_BINS", "MG_DIAG_GAP_BINS"):
+        assert int(macros[name]) == getattr(abi, name), name
+    assert abi.MG_DIAG_SITES == len(mg.SITES)
+    assert abi.MG_DIAG_BINS == mg.DIAG_BINS and abi.MG_DIAG_GAP_BINS == mg.DIAG_GAP_BINS
+
+
 def test_layout():
     assert P.bfp_layout(2, 4095, 32) == (4128, 4128 * 4097 * 4)
     assert P.bfp_layout(2, 31, 16) == (64, 64 * 33 * 2)

@@ -250,6 +250,9 @@ def main():
         del Hs, xw
         torch.cuda.empty_cache()
 
+    # ----------------------------------------- solve diagnostics -------
+    diagnostics = bench_diag(P, torch, f, L, timed, stream)
+
     # --------------------------------------------------- batched solves ---
     batch = None
     if args.batch > 0:
@@ -320,6 +323,7 @@ def main():
         "solve_3d": solve3d,
         "c1_33x33": c1,
         "sweep": sweep,
+        "diagnostics": diagnostics,
         "batched": batch,
         "serving": serving,
         "cpu_baseline": cpu,
@@ -477,6 +481,69 @@ def bench_fp64(P, torch, f, L, us, h2, disc, stream, ev):
     return {"what": "FP64 FMG, same schedule and coefficients, torch tensor ops on the same GPU",
             "ms": round(ms, 3), "dof_per_s": dof / (ms * 1e-3),
             "err_over_disc": round(err / disc, 4)}
+
+
+# The estimates table's extra window bits w*_add per call site (Section 6.3,
+# Table 1), in the order of the diagnostics sites: IR residual (first /
+# later iteration), IR correction, relaxation, V residual, restriction,
+# V correction, FMG prolongation.
+W_ADD_STAR = (5, 4, 0, 2, 4, 6, 1, 0)
+DIAG_SITES = ("ir_res_first", "ir_res", "ir_corr", "relax", "v_res", "restrict", "v_corr",
+              "fmg_prol")
+
+
+def bench_diag(P, torch, f, L, timed, stream):
+    """The recomputation table of Section 6.3 for this problem: one FMG with
+    qcomp for every call, its finest-level window gaps read from the device
+    diagnostics, and the calls Algorithm 1 would recompute with
+    w_tmp = w_out + min(w*_add, w_add_max); plus the nnqcomp saturations of
+    one step of the timed solve."""
+    def make_diag(policy):
+        p = P.mg_params_init(2, L, 32, True, 1, 0, 2, policy, 23)
+        p.min_storage_bits = 32
+        P.bfp_tuning_set("diagnostics", 1)
+        try:
+            return P.Hierarchy(p)
+        finally:
+            P.bfp_tuning_set("diagnostics", 0)
+
+    Hq = make_diag(P.MG_POLICY_Q)
+    Hq.fmg_f64(f[1:], stream)
+    d = Hq.diagnostics(reset=True, stream=stream)[L]
+    gaps = P.abi.MG_DIAG_GAP_BINS
+
+    def recomputed(site, w_add):
+        row = d[site]
+        return int(row[0]) + int(row[2 + w_add:gaps].sum())
+
+    table = {}
+    for cap in (None, 4, 2, 0):
+        per = {DIAG_SITES[k]: recomputed(k, W_ADD_STAR[k] if cap is None else min(W_ADD_STAR[k], cap))
+               for k in range(len(DIAG_SITES))}
+        table["inf" if cap is None else str(cap)] = {"total": sum(per.values()),
+                                                     "per_site": {k: v for k, v in per.items() if v}}
+    xq = P.Vec(2, (1 << L) - 1, Hq.get_vec(L, 0).w, 32)
+    ms_q = timed(Hq, xq, 3, 1)
+    del Hq, xq
+    torch.cuda.empty_cache()
+    Hd = make_diag(P.MG_POLICY_NN_IR_FIRST_Q)      # the timed solve's configuration
+    xd = P.Vec(2, (1 << L) - 1, Hd.get_vec(L, 0).w, 32)
+    ms_d = timed(Hd, xd, 3, 1)
+    Hd.diagnostics(reset=True, stream=stream)
+    timed(Hd, xd, 1, 0)
+    dh = Hd.diagnostics(reset=True, stream=stream)
+    del Hd, xd
+    torch.cuda.empty_cache()
+    return {"what": "finest-level (j = %d) qcomp calls of one FMG with qcomp everywhere "
+                    "(progressive widths, N = 2 IR-V(1,0)) that Algorithm 1 recomputes with "
+                    "w_tmp = w_out + min(w*_add, w_add_max), w*_add from the estimates table; "
+                    "and the nnqcomp saturations of one step of the timed solve" % L,
+            "qcomp_calls_finest": int(d[:, :gaps].sum()),
+            "recomputations_by_w_add_max": table,
+            "all_qcomp_fmg_ms": round(ms_q, 3),
+            "timed_solve_ms_with_diagnostics": round(ms_d, 3),
+            "timed_solve_nnqcomp_calls": int(dh[:, :, P.abi.MG_DIAG_BINS - 3].sum()),
+            "timed_solve_saturated_entries": int(dh[:, :, P.abi.MG_DIAG_BINS - 2].sum())}
 
 
 def bench_c1(P, W, torch, dev, stream, ev):

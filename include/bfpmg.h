@@ -333,8 +333,11 @@ int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream);
  * mg_diag_read synchronizes `stream`, copies the counters to host_out
  * (int64, [MG_MAX_LEVELS + 1][MG_DIAG_SITES][MG_DIAG_BINS], row 0 unused)
  * and, when reset != 0, zeroes them. Counters start at zero when the
- * hierarchy is created. BFP_EINVAL for a NULL argument. Work that is still
- * running on other streams is not waited for.                            */
+ * hierarchy is created. Only hierarchies created with the tuning key
+ * "diagnostics" set keep them (each diagnosed call ends with a few
+ * device-scope atomic adds, which cost a few percent of a solve).
+ * BFP_EINVAL for a NULL argument or a hierarchy without diagnostics. Work
+ * still running on other streams is not waited for.                      */
 #define MG_DIAG_SITES 8
 #define MG_DIAG_BINS 64
 #define MG_DIAG_GAP_BINS 61
@@ -442,7 +445,10 @@ int mg_server_destroy(mg_server* s);
  * "star3d_small_n" = grid size below which every wave takes a single row
  * (values >= 1); "exec_max_points" = largest grid (in interior points) whose
  * level runs inside the one-workgroup coarse-level programs a hierarchy
- * records at creation (0 = never; read by mg_hierarchy_bytes/create).     */
+ * records at creation (0 = never; read by mg_hierarchy_bytes/create);
+ * "diagnostics" = 1: hierarchies created while it is set keep the solve
+ * diagnostics of mg_diag_read (0, the default: none, and no cost; read by
+ * mg_hierarchy_bytes/create, which must see the same value).              */
 int bfp_tuning_set(const char* key, int value);
 
 /* Human-readable description of the last error on this thread.           */

@@ -32,6 +32,11 @@ static int g_exec_max_points = 4096;
 
 int exec_max_points() { return g_exec_max_points; }
 
+// Hierarchies created while this is set keep solve diagnostics.
+static int g_diagnostics = 0;
+
+bool diagnostics_on() { return g_diagnostics != 0; }
+
 // While a sink is installed (on this host thread), the operations append
 // their launch descriptions to it instead of launching.
 static thread_local std::vector<ExecOp>* g_rec = nullptr;
@@ -579,6 +584,11 @@ int bfp_tuning_set(const char* key, int value) {
   if (value < 0 || value > 1 << 20) return fail(BFP_EINVAL, "value out of range");
   const std::string k(key);
   if (k == "exec_max_points") { g_exec_max_points = value; return BFP_OK; }
+  if (k == "diagnostics") {
+    if (value > 1) return fail(BFP_EINVAL, "diagnostics is 0 or 1");
+    g_diagnostics = value;
+    return BFP_OK;
+  }
   if (value < 1) return fail(BFP_EINVAL, "value out of range");
   if (k == "star2d_rows") g_star2d_rows_large = value;
   else if (k == "star2d_small_n") g_star2d_small_n = value;

@@ -37,6 +37,8 @@ bool recording();
 // Diagnostic counters (kDiagBins) that the next operations issued on this
 // host thread count into; null turns the counting off.
 void set_diag_row(int64_t* row);
+// Whether hierarchies created now keep diagnostics (tuning key "diagnostics").
+bool diagnostics_on();
 // grids of at most this many points run inside recorded programs (0: never)
 int exec_max_points();
 // Give every op of a recorded program the slots of its metadata blocks in

@@ -355,15 +355,15 @@ struct Resolved {
   int64_t sa;    // single-term shift when there is no y
 };
 
-// nu / zero: gamma_nu of the op's estimate (used in saturate mode)
 template <class MA>
-__device__ __forceinline__ Resolved resolve_nu(const OpArgs& p, const MA& ma, int64_t nu,
-                                               bool zero) {
+__device__ __forceinline__ Resolved resolve(const OpArgs& p, const MA& ma) {
   Resolved r;
   r.ea = p.alpha_e + p.e_A + ma(kOpX, kMetaExp);
   r.eb = p.has_y ? p.beta_e + ma(kOpY, kMetaExp) : r.ea;
   r.ez = r.ea < r.eb ? r.ea : r.eb;
   if (p.mode == kModeSat) {
+    bool zero;
+    int64_t nu = gamma_nu(p.g, ma, &zero);
     r.eo = zero ? r.ez + 1 - p.w_out : nu - p.w_out;
   } else if (p.mode == kModeQ2) {
     r.eo = r.ez + ma(kOpZ, kMetaMu) - p.w_out;
@@ -379,13 +379,6 @@ __device__ __forceinline__ Resolved resolve_nu(const OpArgs& p, const MA& ma, in
   r.sa = p.mode == kModeAssign ? 0 : r.ea - r.eo;
   r.cmb = make_combine(r.ea - r.eo, r.eb - r.eo);
   return r;
-}
-
-template <class MA>
-__device__ __forceinline__ Resolved resolve(const OpArgs& p, const MA& ma) {
-  bool zero = true;
-  const int64_t nu = p.mode == kModeSat ? gamma_nu(p.g, ma, &zero) : 0;
-  return resolve_nu(p, ma, nu, zero);
 }
 
 __device__ __forceinline__ PtrMeta ptr_meta(const OpArgs& p) {

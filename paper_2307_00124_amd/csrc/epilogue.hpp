@@ -105,7 +105,9 @@ __device__ __forceinline__ void with_fast(const E& e, F&& body) {
   else body(std::integral_constant<int, kVarGen>());
 }
 
-template <int PASS, bool HASY>
+// DG = false compiles the diagnostic counting out (the executor's plain
+// programs); launched kernels keep it behind a null check.
+template <int PASS, bool HASY, bool DG = true>
 struct Epi {
   Resolved R;
   int64_t alpha_m, beta_m, lo, hi;
@@ -133,12 +135,7 @@ struct Epi {
 
   template <class MA>
   __device__ __forceinline__ void init(const OpArgs& op, const MA& ma) {
-    // gamma_nu once: the saturate mode's output exponent, and the window
-    // gap a diagnosed qcomp call counts
-    const bool gap = op.diag && op.mode == kModeQ2;
-    bool zero = true;
-    const int64_t nu = (op.mode == kModeSat || gap) ? gamma_nu(op.g, ma, &zero) : 0;
-    R = resolve_nu(op, ma, nu, zero);
+    R = resolve(op, ma);
     alpha_m = op.alpha_m;
     beta_m = op.beta_m;
     lo = op.lo;
@@ -185,10 +182,18 @@ struct Epi {
     tmu = 1;
     // diagnostics: the window gap of a qcomp call with an estimate (the
     // second pass knows mu* = eo - ez + w_out), or an nnqcomp call
-    diag = op.diag;
-    // mu* = eo - ez + w_out in the second qcomp pass
-    dbin = gap && !zero ? diag_gap_bin(nu - R.ez - (R.eo - R.ez + op.w_out)) : -1;
-    dsat = diag && op.mode == kModeSat;
+    diag = DG ? op.diag : nullptr;
+    dbin = -1;
+    dsat = 0;
+    if (DG && diag) {   // off the common path: only hierarchies that keep diagnostics
+      if (op.mode == kModeQ2) {
+        bool zero;
+        const int64_t nu = gamma_nu(op.g, ma, &zero);
+        // mu* = eo - ez + w_out in the second qcomp pass
+        if (!zero) dbin = diag_gap_bin(nu - R.ez - (R.eo - R.ez + op.w_out));
+      }
+      dsat = op.mode == kModeSat;
+    }
   }
 
   __device__ __forceinline__ int64_t mul_a(int64_t g) const { return alpha_m * g; }

@@ -102,8 +102,8 @@ struct PendingDiag {
   int64_t nsat;
 };
 
-template <int NT, int PASS, bool HASY>
-__device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm,
+template <int NT, int PASS, bool HASY, bool DG>
+__device__ __forceinline__ void ex_finish(const Epi<PASS, HASY, DG>& E, MetaRow& zm,
                                           PendingDiag& pend) {
   constexpr int kExWaves = NT / 64;
   __shared__ Red<NT> R;
@@ -135,7 +135,7 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm,
         zm[kMetaMin] = mn;
         zm[kMetaSat] = st;
         zm[kMetaExp] = E.R.eo;
-        if (E.diag) pend = PendingDiag{E.diag, E.dbin, E.dsat, st};
+        if (DG && E.diag) pend = PendingDiag{E.diag, E.dbin, E.dsat, st};
       }
     }
   }
@@ -149,11 +149,11 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY>& E, MetaRow& zm,
 // Points are enumerated on a 2^lg >= n padded index space; a padding slot
 // becomes the interior point (1, 1, 1), which keeps every address in bounds,
 // and is neither stored nor counted.
-template <int NT, int ND, int PASS, bool HASY, int U, typename Gather>
+template <int NT, int ND, int PASS, bool HASY, bool DG, int U, typename Gather>
 __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uintptr_t base,
                                         int n, const void* yp, int ybits, int64_t py, void* zp0,
                                         int zbits, int64_t pz, Gather&& gather) {
-  Epi<PASS, HASY> E;
+  Epi<PASS, HASY, DG> E;
   E.init(op, ma);
   const Src ys = src_of(yp, ybits, base);
   void* zp = rel(zp0, base);
@@ -196,7 +196,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   ex_finish<NT>(E, ma.lm[ma.s[kOpZ]], *ma.pend);
 }
 
-template <int NT, int ND, int PASS, bool HASY>
+template <int NT, int ND, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
@@ -205,7 +205,7 @@ __device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, c
   int32_t t[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, 4>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, 4>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t b = (ND == 3 ? (int64_t)z * side + y : (int64_t)y) * px + x;
     int64_t g = (int64_t)t[0] * ldx(xs, b) + (int64_t)t[1] * ldx(xs, b - 1) +
@@ -222,7 +222,7 @@ __device__ __forceinline__ constexpr int tidx(int iz, int iy, int ix) {
 }
 
 // restriction: z[I] = sum_o t[o] x[2I + o] over the 3^ND offsets
-template <int NT, int ND, int PASS, bool HASY>
+template <int NT, int ND, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
@@ -230,7 +230,7 @@ __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArg
   int32_t t[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
+  ex_loop<NT, ND, PASS, HASY, DG, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
                                                L.py, L.z, L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
     int64_t g = 0;
 #pragma unroll
@@ -251,7 +251,7 @@ __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArg
 // where along an even dimension only e = 0 contributes (offset 0) and along
 // an odd one e selects the offset 2e - 1. The tap of each corner is chosen
 // from the parities with selects, so the loads stay branch-free.
-template <int NT, int ND, int PASS, bool HASY>
+template <int NT, int ND, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
@@ -259,7 +259,7 @@ __device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs
   int32_t t[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
+  ex_loop<NT, ND, PASS, HASY, DG, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
                                                L.py, L.z, L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
     const int qz = z & 1, qy = y & 1, qx = x & 1;
     const int jz = z >> 1, jy = y >> 1, jx = x >> 1;
@@ -290,12 +290,12 @@ __device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs
   });
 }
 
-template <int NT, int ND, int PASS, bool HASY>
+template <int NT, int ND, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
   const int64_t px = L.px, side = L.n + 2;
-  ex_loop<NT, ND, PASS, HASY, 4>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, 4>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
     return ldx(xs, row * px + x);
@@ -317,18 +317,18 @@ __device__ __forceinline__ OpArgs with_mode(const OpArgs& a, int mode) {
   return op;
 }
 
-template <int NT, int ND, int PASS, bool HASY>
+template <int NT, int ND, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, PendingDiag* pend,
                                             int mode, uintptr_t base) {
   const LdsMeta ma = lds_meta(lm, pend, op.slot);
   if (op.kind == kExStar) {
-    ex_star<NT, ND, PASS, HASY>(op.u.star, with_mode(op.u.star.op, mode), ma, base);
+    ex_star<NT, ND, PASS, HASY, DG>(op.u.star, with_mode(op.u.star.op, mode), ma, base);
   } else if (op.kind == kExPoint) {
-    ex_point<NT, ND, PASS, HASY>(op.u.pt, with_mode(op.u.pt.op, mode), ma, base);
+    ex_point<NT, ND, PASS, HASY, DG>(op.u.pt, with_mode(op.u.pt.op, mode), ma, base);
   } else {
     const OpArgs a = with_mode(op.u.tr.op, mode);
-    if (op.u.tr.kind == 1) ex_restrict<NT, ND, PASS, HASY>(op.u.tr, a, ma, base);
-    else ex_prolong<NT, ND, PASS, HASY>(op.u.tr, a, ma, base);
+    if (op.u.tr.kind == 1) ex_restrict<NT, ND, PASS, HASY, DG>(op.u.tr, a, ma, base);
+    else ex_prolong<NT, ND, PASS, HASY, DG>(op.u.tr, a, ma, base);
   }
 }
 
@@ -432,7 +432,7 @@ static_assert(sizeof(ExecOp) % 4 == 0 && kOpWords <= kBatchThreads, "ExecOp copy
 
 // Run one program (ops[0..count), metadata table metas[0..nmeta)) with this
 // workgroup; pointers are relocated by `base`.
-template <int NT, int ND>
+template <int NT, int ND, bool DG>
 __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int count,
                                             int64_t* const* __restrict__ metas, int nmeta,
                                             uintptr_t base, const double* const* rhs) {
@@ -440,7 +440,7 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
   __shared__ ExecOp buf[2];
   __shared__ PendingDiag pend;
   const int t = threadIdx.x;
-  if (t == 0) pend.diag = nullptr;
+  if (DG && t == 0) pend.diag = nullptr;
   const uint32_t* gw = reinterpret_cast<const uint32_t*>(ops);
   uint32_t* bw = reinterpret_cast<uint32_t*>(buf);
   for (int i = t; i < nmeta * kExMetaF; i += NT)
@@ -452,7 +452,7 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
     const bool pre = t < kOpWords && k + 1 < count;
     const uint32_t nextw = pre ? gw[(int64_t)(k + 1) * kOpWords + t] : 0;
     const ExecOp& op = buf[k & 1];
-    if (t == 0 && pend.diag) {   // the previous op's diagnostic counts
+    if (DG && t == 0 && pend.diag) {   // the previous op's diagnostic counts
       diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);
       pend.diag = nullptr;
     }
@@ -466,16 +466,16 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
                                                                  : op.u.tr.op.has_y);
       if (op.mode == kExModeQ) {
         if (hasy) {
-          ex_dispatch<NT, ND, kQ1, true>(op, lm, &pend, kModeQ1, base);
-          ex_dispatch<NT, ND, kOut, true>(op, lm, &pend, kModeQ2, base);
+          ex_dispatch<NT, ND, kQ1, true, DG>(op, lm, &pend, kModeQ1, base);
+          ex_dispatch<NT, ND, kOut, true, DG>(op, lm, &pend, kModeQ2, base);
         } else {
-          ex_dispatch<NT, ND, kQ1, false>(op, lm, &pend, kModeQ1, base);
-          ex_dispatch<NT, ND, kOut, false>(op, lm, &pend, kModeQ2, base);
+          ex_dispatch<NT, ND, kQ1, false, DG>(op, lm, &pend, kModeQ1, base);
+          ex_dispatch<NT, ND, kOut, false, DG>(op, lm, &pend, kModeQ2, base);
         }
       } else if (hasy) {
-        ex_dispatch<NT, ND, kOut, true>(op, lm, &pend, op.mode, base);
+        ex_dispatch<NT, ND, kOut, true, DG>(op, lm, &pend, op.mode, base);
       } else {
-        ex_dispatch<NT, ND, kOut, false>(op, lm, &pend, op.mode, base);
+        ex_dispatch<NT, ND, kOut, false, DG>(op, lm, &pend, op.mode, base);
       }
     }
     if (pre) bw[((k + 1) & 1) * kOpWords + t] = nextw;
@@ -483,10 +483,11 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
   }
   for (int i = t; i < nmeta * kExMetaF; i += NT)
     ((BFP_GLOBAL int64_t*)rel(metas[i / kExMetaF], base))[i % kExMetaF] = lm[i / kExMetaF][i % kExMetaF];
-  if (t == 0 && pend.diag) diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);
+  if (DG && t == 0 && pend.diag) diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);
 }
 
-template <int ND>
+// DG: the program counts diagnostics (otherwise their code is compiled out)
+template <int ND, bool DG>
 __global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict__ ops, int count,
                                                       int64_t* const* __restrict__ metas,
                                                       int nmeta, ExecRhs rhs) {
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict_
   // the program runner's first barrier)
   __shared__ const double* srhs[kMaxLevels];
   if (threadIdx.x < kMaxLevels) srhs[threadIdx.x] = rhs.p[threadIdx.x];
-  run_program<kExecThreads, ND>(ops, count, metas, nmeta, 0, srhs);
+  run_program<kExecThreads, ND, DG>(ops, count, metas, nmeta, 0, srhs);
 }
 
 template <int ND>
@@ -502,8 +503,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_exec_batch(
     const BatchEntry* __restrict__ entries, const ExecOp* __restrict__ ops,
     int64_t* const* __restrict__ metas, const double* const* __restrict__ rhs_table) {
   const BatchEntry& E = entries[blockIdx.x];
-  run_program<kBatchThreads, ND>(ops + E.op_begin, E.op_count, metas + E.meta_begin, E.nmeta,
-                                 E.base, rhs_table + (int64_t)E.prob * kMaxLevels);
+  run_program<kBatchThreads, ND, false>(ops + E.op_begin, E.op_count, metas + E.meta_begin,
+                                        E.nmeta, E.base, rhs_table + (int64_t)E.prob * kMaxLevels);
 }
 
 }  // namespace
@@ -522,15 +523,16 @@ hipError_t launch_exec_batch(const BatchEntry* entries_dev, int nentries, const 
 }
 
 hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_dev, int nmeta,
-                       int ndim, const ExecRhs* rhs, hipStream_t s) {
+                       int ndim, const ExecRhs* rhs, bool diag, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (nmeta < 1 || nmeta > kExecMaxMeta) return hipErrorInvalidValue;
   ExecRhs r{};
   if (rhs) r = *rhs;
-  if (ndim == 2)
-    hipLaunchKernelGGL(k_exec<2>, dim3(1), dim3(kExecThreads), 0, s, ops_dev, count, metas_dev, nmeta, r);
-  else
-    hipLaunchKernelGGL(k_exec<3>, dim3(1), dim3(kExecThreads), 0, s, ops_dev, count, metas_dev, nmeta, r);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(kExecThreads), 0, s, ops_dev, count, metas_dev, nmeta, r);
+  };
+  if (ndim == 2) diag ? go(k_exec<2, true>) : go(k_exec<2, false>);
+  else diag ? go(k_exec<3, true>) : go(k_exec<3, false>);
   return hipGetLastError();
 }
 

@@ -156,8 +156,9 @@ constexpr int kExMetaF = 8;
 struct ExecRhs {
   const double* p[16];
 };
+// diag: some ops of the program count diagnostics (their OpArgs::diag)
 hipError_t launch_exec(const ExecOp* ops_dev, int count, int64_t* const* metas_dev, int nmeta,
-                       int ndim, const ExecRhs* rhs, hipStream_t s);
+                       int ndim, const ExecRhs* rhs, bool diag, hipStream_t s);
 
 // Batched programs: one workgroup of kBatchThreads threads per problem runs
 // that problem's program. Programs are relocatable: every data and metadata

@@ -220,7 +220,8 @@ int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, Site
 
 int run_program(mg_hierarchy* h, const Program& pg, hipStream_t s,
                 const ExecRhs* rhs = nullptr) {
-  int rc = hip_check(launch_exec(pg.ops, pg.count, pg.metas, pg.nmeta, h->prm.ndim, rhs, s),
+  int rc = hip_check(launch_exec(pg.ops, pg.count, pg.metas, pg.nmeta, h->prm.ndim, rhs,
+                                h->diag != nullptr, s),
                      "coarse-level program");
   if (rc) return rc;
   h->bytes += pg.bytes;
@@ -728,7 +729,7 @@ int bfpk::hierarchy_bytes_ex(const mg_params* prm, int64_t exec_points, size_t* 
   size_t nops = 0;
   if ((rc = count_ops(prm, exec_points, &nops))) return rc;
   mg_hierarchy tmp;
-  *bytes = layout(&tmp, prm, nullptr, nops, true);
+  *bytes = layout(&tmp, prm, nullptr, nops, diagnostics_on());
   return BFP_OK;
 }
 
@@ -743,12 +744,13 @@ int bfpk::hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t byte
   mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
   if (!h) return fail(BFP_ENOMEM, "host allocation failed");
   if ((rc = setup(h, prm, exec_points))) { delete h; return rc; }
-  const size_t need = layout(h, prm, nullptr, nops, true);
+  const bool diag = diagnostics_on();
+  const size_t need = layout(h, prm, nullptr, nops, diag);
   if (bytes < need) {
     delete h;
     return fail(BFP_ENOMEM, "arena holds %zu bytes, the hierarchy needs %zu", bytes, need);
   }
-  layout(h, prm, static_cast<char*>(arena_dev), nops, true);
+  layout(h, prm, static_cast<char*>(arena_dev), nops, diag);
   hipStream_t s = (hipStream_t)stream;
   for (int j = 1; j <= prm->L; ++j) {
     Level& L = h->lv[j];
@@ -756,7 +758,7 @@ int bfpk::hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t byte
       if ((rc = bfp_vec_init(v, stream))) { delete h; return rc; }
     }
   }
-  if ((rc = hip_check(hipMemsetAsync(h->diag, 0, kDiagBytes, s), "diagnostics reset"))) {
+  if (h->diag && (rc = hip_check(hipMemsetAsync(h->diag, 0, kDiagBytes, s), "diagnostics reset"))) {
     delete h;
     return rc;
   }
@@ -893,7 +895,9 @@ int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream) {
 
 int mg_diag_read(mg_hierarchy* h, int64_t* host_out, int reset, void* stream) {
   if (!h || !host_out) return fail(BFP_EINVAL, "NULL argument");
-  if (!h->diag) return fail(BFP_EINVAL, "this hierarchy keeps no diagnostics");
+  if (!h->diag)
+    return fail(BFP_EINVAL, "this hierarchy keeps no diagnostics (created with tuning key "
+                            "\"diagnostics\" = 0)");
   hipStream_t s = (hipStream_t)stream;
   int rc = hip_check(hipStreamSynchronize(s), "diagnostics read");
   if (!rc) rc = hip_check(hipMemcpy(host_out, h->diag, kDiagBytes, hipMemcpyDeviceToHost),

@@ -10,25 +10,11 @@
 
 #include "epilogue.hpp"
 
-#include <utility>
-
 namespace bfpk {
 
 template <int ND>
 __device__ __forceinline__ int tap_index(const int (&o)[3]) {
   return ND == 2 ? (o[1] + 1) * 3 + (o[2] + 1) : ((o[0] + 1) * 3 + (o[1] + 1)) * 3 + (o[2] + 1);
-}
-
-// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): loops
-// whose indices are compile-time constants from the start, so the arrays
-// they index stay in registers whatever the optimizer's unrolling decides
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>()), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>());
 }
 
 // one coarse output point per thread; work items: (output row, run of 256 points) pairs, grid-strided over at
@@ -94,49 +80,50 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const TransferLaunch L) {
     if (ND == 3) { cz = row / cells; cy = row % cells; } else { cy = row; }
     if (cx >= cells) continue;
     int64_t cv[2][2][2];
-    static_for<ND == 3 ? 2 : 1>([&](auto ez_) {
-      constexpr int ez = decltype(ez_)::value;
-      static_for<2>([&](auto ey_) {
-        constexpr int ey = decltype(ey_)::value;
+#pragma unroll
+    for (int ez = 0; ez < (ND == 3 ? 2 : 1); ++ez)
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey) {
         const int64_t crow = ND == 3 ? (cz + ez) * sc + (cy + ey) : (cy + ey);
         cv[ez][ey][0] = X[crow * L.px + cx];
         cv[ez][ey][1] = X[crow * L.px + cx + 1];
-      });
-    });
-    static_for<ND == 3 ? 2 : 1>([&](auto dz_) {
-      constexpr int dz = decltype(dz_)::value;
-      static_for<2>([&](auto dy_) {
-        constexpr int dy = decltype(dy_)::value;
+      }
+#pragma unroll
+    for (int dz = 0; dz < (ND == 3 ? 2 : 1); ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
         const int64_t fz = 2 * cz + dz, fy = 2 * cy + dy;
         const bool row_in = (ND == 2 || (fz >= 1 && fz <= nf)) && fy >= 1 && fy <= nf;
         const int64_t frow = ND == 3 ? fz * sf + fy : fy;
-        static_for<2>([&](auto dx_) {
-          constexpr int dx = decltype(dx_)::value;
+        int64_t outv[2] = {0, 0};
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
           const int64_t fx = 2 * cx + dx;
-          if (!row_in || fx < 1 || fx > nf) return;
-          // corner (ez, ey, ex) contributes along the odd dimensions only
+          if (!row_in || fx < 1 || fx > nf) continue;
           int64_t g = 0;
-          static_for<(ND == 3 && dz) ? 2 : 1>([&](auto ez_) {
-            constexpr int ez = decltype(ez_)::value;
-            static_for<dy ? 2 : 1>([&](auto ey_) {
-              constexpr int ey = decltype(ey_)::value;
-              static_for<dx ? 2 : 1>([&](auto ex_) {
-                constexpr int ex = decltype(ex_)::value;
-                constexpr int o0 = ND == 3 ? (dz ? 2 * ez - 1 : 0) : 0;
-                constexpr int o1 = dy ? 2 * ey - 1 : 0;
-                constexpr int o2 = dx ? 2 * ex - 1 : 0;
-                constexpr int ti = ND == 2 ? (o1 + 1) * 3 + (o2 + 1)
-                                           : ((o0 + 1) * 3 + (o1 + 1)) * 3 + (o2 + 1);
-                g += (int64_t)L.taps[ti] * cv[ez][ey][ex];
-              });
-            });
-          });
+          int o[3];
+#pragma unroll
+          for (int ez = 0; ez < 2; ++ez) {
+            if (ND == 2 && ez) continue;
+            if (ND == 3 && !dz && ez) continue;
+#pragma unroll
+            for (int ey = 0; ey < 2; ++ey) {
+              if (!dy && ey) continue;
+#pragma unroll
+              for (int ex = 0; ex < 2; ++ex) {
+                if (!dx && ex) continue;
+                o[0] = ND == 3 ? (dz ? 2 * ez - 1 : 0) : 0;
+                o[1] = dy ? 2 * ey - 1 : 0;
+                o[2] = dx ? 2 * ex - 1 : 0;
+                g += (int64_t)L.taps[tap_index<ND>(o)] * cv[ez][ey][ex];
+              }
+            }
+          }
           const int64_t yv = HASY ? (int64_t)Y[frow * L.py + fx] : 0;
-          const int64_t v = E.template put<VAR>(g, yv, true);
-          if (PASS != kQ1) Z[frow * L.pz + fx] = (TZ)v;
-        });
-      });
-    });
+          outv[dx] = E.template put<VAR>(g, yv, true);
+          if (PASS != kQ1) Z[frow * L.pz + fx] = (TZ)outv[dx];
+        }
+      }
   }
   });
   E.finish();

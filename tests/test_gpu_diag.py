@@ -23,7 +23,11 @@ POLICY = {"q": P.MG_POLICY_Q, "nn": P.MG_POLICY_NN, "nn_ir_first_q": P.MG_POLICY
 def _pair(ndim, L, w, progressive, policy, nu1, nu2, eta):
     p = P.mg_params_init(ndim, L, w, progressive, nu1, nu2, 2, POLICY[policy], eta)
     f = {j: W.manufactured_f(j, ndim) for j in range(1, L + 1)}
-    H = P.Hierarchy(p)
+    P.bfp_tuning_set("diagnostics", 1)
+    try:
+        H = P.Hierarchy(p)
+    finally:
+        P.bfp_tuning_set("diagnostics", 0)
     for j in range(1, L + 1):
         H.set_rhs(j, torch.from_numpy(np.ascontiguousarray(f[j])).cuda())
     widths = mg.widths_progressive(L, w) if progressive else mg.widths_fixed(L, w)
@@ -66,6 +70,13 @@ def test_ir_diagnostics_and_reset():
     _same(d, O, 5, "IR")
     assert int(d[5, 0].sum()) == 0 and int(d[5, 1, :mg.DIAG_GAP_BINS].sum()) == 9
     assert not H.diagnostics().any()
+
+
+def test_off_by_default():
+    p = P.mg_params_init(2, 4, 24, True, 1, 0, 2, P.MG_POLICY_NN, 23)
+    H = P.Hierarchy(p)
+    with pytest.raises(P.BFPError):
+        H.diagnostics()
 
 
 def test_fmg_f64_counts_like_separate_calls():

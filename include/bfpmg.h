@@ -314,6 +314,20 @@ int mg_fmg(mg_hierarchy* h, void* stream);
  * events cannot be created.                                              */
 int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream);
 
+/* IR-V with the safety mechanism of Section 6.4 (a solver that skips
+ * normalization watches its residual and runs Algorithm 1 — qcomp — for
+ * some operations during some iterations when convergence stalls): like
+ * mg_ir, except that after an iteration whose IR residual saturated any
+ * entry (the nnqcomp estimate was too small) or whose residual norm exceeds
+ * theta = theta_num / 2^theta_log2den times the previous one, the IR
+ * residuals of the next q_iters iterations use qcomp. The norms and the
+ * saturation count are read after every iteration, so the call synchronizes
+ * `stream` once per iteration. *switched (nullable) receives the number of
+ * iterations that ran the fallback. BFP_EINVAL for a bad level, iters < 0,
+ * q_iters < 0, theta_num < 1 or theta_log2den outside [0, 62].           */
+int mg_ir_safe(mg_hierarchy* h, int level, int iters, int q_iters, int32_t theta_num,
+               int32_t theta_log2den, int* switched, void* stream);
+
 /* Diagnostics of the solves run on a hierarchy (Section 4's qcomp window,
  * Table 2, and nnqcomp saturation, Section 6.4), kept on the device by every
  * quantizing call the mg_* functions issue, counted per recursion level

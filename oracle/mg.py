@@ -179,7 +179,10 @@ class Stats:
             a[level, k] = row
         return a
 
+    last_saturated: int = 0      # entries the most recent call saturated
+
     def add(self, site: str, info: blas.QInfo) -> None:
+        self.last_saturated = info.saturated
         self.calls += 1
         self.per_site[site] = self.per_site.get(site, 0) + 1
         if info.mode == "q":
@@ -200,6 +203,7 @@ class Hierarchy:
     nu1: int = 1
     nu2: int = 0
     window: bool = True        # qcomp with the Table 1 window (else plain)
+    ir_res_saturated: int = 0  # entries the last IR residual saturated
     stats: Stats = field(default_factory=Stats)
     A: dict = field(default_factory=dict)
     R: dict = field(default_factory=dict)
@@ -314,6 +318,7 @@ def ir_iteration(H: Hierarchy, l: int, x: BFP, gamma_res: Fraction | None,
     r = _quantize_op(H, "ir_res_first" if first else "ir_res",
                      blas.gemv(H.A[l], x, H.b[l], ONE, MINUS_ONE),
                      H.widths.inner[l], gamma_res, force_q=force_q)
+    H.ir_res_saturated = H.stats.last_saturated
     y = vcycle(H, l, r)
     xn = _quantize_op(H, "ir_corr", blas.sub(x, y), H.widths.work[l],
                       x.norm_inf() + y.norm_inf())
@@ -337,6 +342,37 @@ def fmg(H: Hierarchy, N: int) -> BFP:
             x, r = ir_iteration(H, l, x, g, first=(i == 1))
         r_last = r
     return x
+
+
+def ir_solve_safe(H: Hierarchy, x0: BFP, iters: int, q_iters: int = 2,
+                  theta: Fraction = Fraction(1)) -> tuple[BFP, list, int]:
+    """IR-V with the safety mechanism of Section 6.4: an iterative solver that
+    skips normalization watches the residual, and when convergence stalls it
+    runs Algorithm 1 (qcomp) for some operations during some iterations.
+    Here: after an iteration whose IR residual saturated (nnqcomp's estimate
+    was too small) or whose residual norm exceeds theta times the previous
+    one, the IR residuals of the next q_iters iterations use qcomp. Returns
+    (x, residual history, iterations that ran the fallback)."""
+    x = x0
+    r = None
+    history = []
+    force = 0
+    switched = 0
+    prev = None
+    for i in range(1, iters + 1):
+        g = None if r is None else r.norm_inf()
+        fallback = force > 0
+        force_q = fallback or (H.policy == "nn_ir_first2_q" and i <= 2)
+        x, r = ir_iteration(H, H.L, x, g, force_q=force_q, first=(i == 1))
+        if fallback:
+            switched += 1
+            force -= 1
+        n = r.norm_inf()
+        if H.ir_res_saturated > 0 or (prev is not None and n > Fraction(theta) * prev):
+            force = q_iters
+        prev = n
+        history.append(r)
+    return x, history, switched
 
 
 def ir_solve(H: Hierarchy, x0: BFP, iters: int) -> tuple[BFP, list]:

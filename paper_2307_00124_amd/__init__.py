@@ -340,6 +340,16 @@ class Hierarchy:
     def fmg(self, stream=None) -> None:
         check(lib.mg_fmg(self.h, _stream(stream)), "mg_fmg")
 
+    def ir_safe(self, level: int, iters: int, q_iters: int = 2, theta=(1, 0),
+                stream=None) -> int:
+        """mg_ir_safe: IR-V with the qcomp fallback; theta = (num, k) stands
+        for num / 2^k. Returns the number of iterations that ran the
+        fallback."""
+        sw = C.c_int(0)
+        check(lib.mg_ir_safe(self.h, level, iters, q_iters, int(theta[0]), int(theta[1]),
+                             C.byref(sw), _stream(stream)), "mg_ir_safe")
+        return sw.value
+
     def diagnostics(self, reset: bool = False, stream=None):
         """mg_diag_read: the solve diagnostics as an int64 numpy array
         [level 0..MG_MAX_LEVELS][site][bin] (synchronizes `stream`)."""

@@ -105,6 +105,7 @@ SIGNATURES = {
     "mg_fmg": (I, [VP, VP]),
     "mg_fmg_f64": (I, [VP, VP, VP]),
     "mg_diag_read": (I, [VP, VP, I, VP]),
+    "mg_ir_safe": (I, [VP, I, I, I, I, I, P(I), VP]),
     "mg_ir": (I, [VP, I, I, VP]),
     "mg_vcycle": (I, [VP, I, P(bfp_vec), P(bfp_vec), VP]),
     "mg_get_vec": (I, [VP, I, I, P(bfp_vec)]),

@@ -283,13 +283,14 @@ int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
 }
 
 // one IR-V iteration on level l; gamma = the estimate for the residual
+// (force_q: the IR residual in qcomp whatever the policy)
 int ir_iteration(mg_hierarchy* h, int l, const bfp_gamma* gres, bool first, bool plain_first2,
-                 hipStream_t s) {
+                 hipStream_t s, bool force_q = false) {
   Level& L = h->lv[l];
   int rc;
   const Site site = first ? kIrResFirst : kIrRes;
   int mode = mode_for(h, site, plain_first2);
-  if (!gres) mode = BFP_NORMALIZE;   // no estimate exists: qcomp
+  if (!gres || force_q) mode = BFP_NORMALIZE;   // no estimate exists, or forced: qcomp
   bfp_gamma gdummy{};
   gdummy.rule = BFP_GAMMA_EXPLICIT;
   if ((rc = op_stencil(h, &h->A, L.x, &kOne, &kMinusOne, &L.b, L.r, site, mode,
@@ -842,6 +843,57 @@ int mg_ir(mg_hierarchy* h, int level, int iters, void* stream) {
     int rc = ir_iteration(h, level, i == 1 ? nullptr : &g, i == 1, plain_first2, s);
     if (rc) return rc;
   }
+  return BFP_OK;
+}
+
+// exact: M 2^e > (num / 2^k) Mp 2^ep for M, Mp in [0, 2^31], num in [1, 2^31)
+static bool norm_exceeds(int64_t M, int64_t e, int64_t Mp, int64_t ep, int64_t num, int k) {
+  if (M == 0) return false;
+  const unsigned __int128 B = (unsigned __int128)Mp * (uint64_t)num;   // < 2^62
+  if (B == 0) return true;
+  const int64_t d = e + k - ep;   // compare M 2^d with B
+  if (d >= 64) return true;
+  if (d <= -64) return false;
+  if (d >= 0) return ((unsigned __int128)M << d) > B;
+  return (unsigned __int128)M > (B << -d);
+}
+
+int mg_ir_safe(mg_hierarchy* h, int level, int iters, int q_iters, int32_t theta_num,
+               int32_t theta_log2den, int* switched, void* stream) {
+  if (!h || level < 1 || level > h->prm.L || iters < 0 || q_iters < 0)
+    return fail(BFP_EINVAL, "bad argument");
+  if (theta_num < 1 || theta_log2den < 0 || theta_log2den > 62)
+    return fail(BFP_EINVAL, "theta must be num / 2^k with num >= 1 and 0 <= k <= 62");
+  hipStream_t s = (hipStream_t)stream;
+  Level& L = h->lv[level];
+  int force = 0, nsw = 0, rc;
+  bool have_prev = false;
+  int64_t prevM = 0, preve = 0;
+  int64_t meta[kExMetaF];
+  for (int i = 1; i <= iters; ++i) {
+    const bool fallback = force > 0;
+    bfp_gamma g = g_norm(L.r, kOne);
+    const bool plain_first2 = h->prm.policy == MG_POLICY_NN_IR_FIRST2_Q && i <= 2;
+    if ((rc = ir_iteration(h, level, i == 1 ? nullptr : &g, i == 1, plain_first2, s, fallback)))
+      return rc;
+    if (fallback) {
+      ++nsw;
+      --force;
+    }
+    // the residual's saturations and norm decide the next iterations
+    if ((rc = hip_check(hipMemcpyAsync(meta, L.r.meta, sizeof meta, hipMemcpyDeviceToHost, s),
+                        "residual metadata")) ||
+        (rc = hip_check(hipStreamSynchronize(s), "residual metadata")))
+      return rc;
+    const int64_t M = std::max(meta[kMetaMax], -meta[kMetaMin]);
+    if (meta[kMetaSat] > 0 ||
+        (have_prev && norm_exceeds(M, meta[kMetaExp], prevM, preve, theta_num, theta_log2den)))
+      force = q_iters;
+    have_prev = true;
+    prevM = M;
+    preve = meta[kMetaExp];
+  }
+  if (switched) *switched = nsw;
   return BFP_OK;
 }
 

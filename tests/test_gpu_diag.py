@@ -13,6 +13,7 @@ import paper_2307_00124_amd as P
 import workloads as W
 from oracle import mg
 from oracle.bfp import from_f64
+from tests.gpu_util import assert_block_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -86,3 +87,22 @@ def test_fmg_f64_counts_like_separate_calls():
     H.fmg_f64([torch.from_numpy(np.ascontiguousarray(f[j])).cuda() for j in range(1, 9)])
     b = H.diagnostics()
     assert (a == b).all() and a[8, :, :mg.DIAG_GAP_BINS].sum() + a[8, :, mg.DIAG_NN_CALLS].sum() == 13
+
+
+@pytest.mark.parametrize("ndim,L,w,policy,nu,iters,q_iters,theta", [
+    (2, 6, 24, "nn", (1, 0), 10, 2, (1, 0)),              # saturation triggers
+    (2, 7, 24, "nn", (1, 0), 8, 2, (1, 0)),               # finest level launched
+    (2, 5, 24, "nn_ir_first2_q", (1, 0), 6, 1, (1, 40)),  # norm test triggers every time
+    (3, 4, 24, "nn", (1, 0), 6, 3, (3, 1))])
+def test_safe_ir_matches_oracle(ndim, L, w, policy, nu, iters, q_iters, theta):
+    """IR-V from zero with the qcomp fallback (Section 6.4): the same
+    iterate, last residual and number of fallback iterations as the oracle."""
+    H, O, _ = _pair(ndim, L, w, True, policy, nu[0], nu[1], 23)
+    n = (1 << L) + 1
+    H.set_x(L, torch.zeros((n,) * ndim, dtype=torch.float64, device="cuda"))
+    sw = H.ir_safe(L, iters, q_iters, theta)
+    x, hist, sw_o = mg.ir_solve_safe(O, mg.zero_block(L, ndim, O.widths.work[L]), iters, q_iters,
+                                     Fraction(theta[0], 1 << theta[1]))
+    assert sw == sw_o
+    assert_block_equal(H.get_vec(L, 0), x, "x")
+    assert_block_equal(H.get_vec(L, 2), hist[-1], "last residual")

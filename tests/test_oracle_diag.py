@@ -81,3 +81,52 @@ def test_saturation_counts_add_up():
     assert int(a[:, :, mg.DIAG_NN_SAT].sum()) == H.stats.saturations > 0
     assert 0 < int(a[:, :, mg.DIAG_NN_SAT_CALLS].sum()) <= int(a[:, :, mg.DIAG_NN_CALLS].sum())
     assert int(a[:, :, :mg.DIAG_GAP_BINS].sum()) == 0
+
+
+# ------------------------------------------ safety fallback (Section 6.4) --
+
+def _ir_hier(L, w, policy, nu=(1, 0)):
+    f = {j: W.manufactured_f(j, 2) for j in range(1, L + 1)}
+    return mg.build_hierarchy(f, 2, L, mg.widths_progressive(L, w),
+                              mg.make_smoother(2, Fraction(23, 100)), policy=policy,
+                              nu1=nu[0], nu2=nu[1])
+
+
+def test_safe_ir_recovers_where_plain_nnqcomp_stalls():
+    """IR-V(1,0) from zero with nnqcomp everywhere: the second residual
+    outgrows its estimate and saturates, and the plain iteration stalls at a
+    saturated power of two (the Remark on skipping normalization in IR-V);
+    the fallback reruns the IR residual with qcomp and convergence resumes."""
+    L = 6
+    H = _ir_hier(L, 24, "nn")
+    _, hist = mg.ir_solve(H, mg.zero_block(L, 2, H.widths.work[L]), 8)
+    stalled = [r.norm_inf() for r in hist]
+    assert stalled[2] == stalled[3] == stalled[4] and H.stats.saturations > 0
+    Hs = _ir_hier(L, 24, "nn")
+    _, hs, switched = mg.ir_solve_safe(Hs, mg.zero_block(L, 2, Hs.widths.work[L]), 8)
+    assert switched > 0
+    assert hs[-1].norm_inf() < stalled[3] / 100      # far below the plateau
+
+
+def test_safe_ir_without_a_trigger_is_plain_ir():
+    L = 5
+    H = _ir_hier(L, 24, "q")
+    x, hist = mg.ir_solve(H, mg.zero_block(L, 2, H.widths.work[L]), 6)
+    Hs = _ir_hier(L, 24, "q")
+    xs, hs, switched = mg.ir_solve_safe(Hs, mg.zero_block(L, 2, Hs.widths.work[L]), 6,
+                                        theta=Fraction(16))
+    assert switched == 0 and (xs.m == x.m).all() and xs.e == x.e
+
+
+def test_safe_ir_always_triggered_is_the_qcomp_residual_policy():
+    """With a threshold no residual can meet, every iteration from the third
+    on runs the fallback (the first two IR residuals are qcomp by the
+    policy; the norm test needs a previous residual): exactly the policy
+    that takes qcomp for every IR residual."""
+    L = 5
+    H = _ir_hier(L, 24, "nn_ir_q")
+    x, _ = mg.ir_solve(H, mg.zero_block(L, 2, H.widths.work[L]), 6)
+    Hs = _ir_hier(L, 24, "nn_ir_first2_q")
+    xs, _, switched = mg.ir_solve_safe(Hs, mg.zero_block(L, 2, Hs.widths.work[L]), 6,
+                                       q_iters=1, theta=Fraction(1, 1 << 40))
+    assert switched == 4 and (xs.m == x.m).all() and xs.e == x.e

@@ -252,6 +252,7 @@ def main():
 
     # ----------------------------------------- solve diagnostics -------
     diagnostics = bench_diag(P, torch, f, L, timed, stream)
+    diagnostics["ir_fallback"] = bench_fallback(P, W, torch, dev, stream, ev)
 
     # --------------------------------------------------- batched solves ---
     batch = None
@@ -544,6 +545,41 @@ def bench_diag(P, torch, f, L, timed, stream):
             "timed_solve_ms_with_diagnostics": round(ms_d, 3),
             "timed_solve_nnqcomp_calls": int(dh[:, :, P.abi.MG_DIAG_BINS - 3].sum()),
             "timed_solve_saturated_entries": int(dh[:, :, P.abi.MG_DIAG_BINS - 2].sum())}
+
+
+def bench_fallback(P, W, torch, dev, stream, ev, L=10, iters=12):
+    """IR-V(1,0) from zero on the 1025^2 grid with nnqcomp everywhere (the
+    Remark on skipping normalization in IR-V): plain, and with the qcomp
+    fallback of mg_ir_safe (q_iters = 2, theta = 1); error over the
+    discretization error after `iters` iterations, and the time."""
+    n = (1 << L) + 1
+    us = torch.from_numpy(W.manufactured_u(L, 2)).to(dev)
+    h2 = 2.0 ** (-2 * L)
+    kappa = (math.pi * 2.0 ** -L) ** 2 / (4.0 * math.sin(math.pi * 2.0 ** -L / 2.0) ** 2)
+    disc = (kappa - 1.0) * math.sqrt(float((us[1:-1, 1:-1] ** 2).sum()) * h2)
+    out = {"workload": "2D 1025x1025, IR-V(1,0) from zero, %d iterations, nnqcomp, progressive "
+                       "widths (inner 24)" % iters}
+    for name in ("plain", "fallback"):
+        p = P.mg_params_init(2, L, 24, True, 1, 0, 2, P.MG_POLICY_NN, 23)
+        p.min_storage_bits = 32
+        H = P.Hierarchy(p)
+        for j in range(1, L + 1):
+            H.set_rhs(j, torch.from_numpy(W.manufactured_f(j, 2)).to(dev), stream)
+        H.set_x(L, torch.zeros((n, n), dtype=torch.float64, device=dev), stream)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        sw = H.ir_safe(L, iters, 2, (1, 0), stream) if name == "fallback" else H.ir(L, iters, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        u = P.bfp_vec_to_f64(H.get_vec(L, 0))
+        err = math.sqrt(float(((u - us)[1:-1, 1:-1] ** 2).sum()) * h2)
+        out[name] = {"err_over_disc": round(err / disc, 3), "ms": round(e0.elapsed_time(e1), 3)}
+        if name == "fallback":
+            out[name]["fallback_iterations"] = sw
+        del H
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_c1(P, W, torch, dev, stream, ev):

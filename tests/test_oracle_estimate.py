@@ -1,0 +1,69 @@
+"""Pins of the oracle's a priori precision estimation (Section 6.2,
+Algorithm bfp-prec-est)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import estimate as est
+from oracle import fp64, mg
+
+
+def _fp64_E(j, ndim=2):
+    n = (1 << j) - 1
+    sm = mg.make_smoother(ndim, Fraction(23, 100))
+    zeros = {l: np.zeros(((1 << l) + 1,) * ndim) for l in range(1, j + 1)}
+    M = fp64.FP64MG(zeros, ndim, j, float(sm.c1.value), float(sm.c2.value))
+    cols = []
+    for k in range(n ** ndim):
+        e = np.zeros(((1 << j) + 1,) * ndim)
+        e[tuple(c + 1 for c in np.unravel_index(k, (n,) * ndim))] = 1.0
+        cols.append(M.ir(j, e)[(slice(1, -1),) * ndim].ravel())
+    return np.stack(cols, axis=1)
+
+
+def test_energy_rate_is_the_A_norm():
+    """||E||_A = ||A^(1/2) E A^(-1/2)||_2, computed here through A's own
+    eigendecomposition (a different route than the generalized eigenproblem)."""
+    A = est.dense_A(3, 2)
+    lam, Q = np.linalg.eigh(A)
+    half = Q @ np.diag(np.sqrt(lam)) @ Q.T
+    mhalf = Q @ np.diag(1 / np.sqrt(lam)) @ Q.T
+    for E in (_fp64_E(3), np.random.default_rng(0).standard_normal(A.shape)):
+        assert est.energy_rate(E, A) == pytest.approx(np.linalg.norm(half @ E @ mhalf, 2), rel=1e-10)
+
+
+def test_dense_operator_is_the_scaled_five_point_stencil():
+    A = est.dense_A(2, 2)
+    assert A.shape == (9, 9) and (np.diag(A) == 1.0).all()
+    assert A[4, 1] == A[4, 3] == A[4, 5] == A[4, 7] == -0.25 and A[0, 4] == 0.0
+    assert np.allclose(A, A.T) and np.linalg.eigvalsh(A).min() > 0
+
+
+@pytest.mark.parametrize("j", [3, 4])
+def test_wide_bfp_rate_equals_the_fp64_vcycle_rate(j):
+    """With 32-bit widths on every level the BFP V-cycle's error propagation
+    differs from the FP64 one only by rounding: the rates agree to 1e-6."""
+    wide = mg.Widths(*({l: 32 for l in range(1, j + 1)},) * 3)
+    assert est.conv_rate_v_cycle(2, j, wide) == pytest.approx(est.energy_rate(_fp64_E(j), est.dense_A(j, 2)),
+                                                              rel=1e-6)
+
+
+def test_width_rules():
+    wd = est.width_rules(5, 2, 3)
+    assert wd.work == {1: 10, 2: 12, 3: 14, 4: 16, 5: 18}
+    assert wd.check == {l: max(wd.work[l], min(32, 3 * l + 2)) for l in range(1, 6)}
+    assert wd.inner == {l: min(wd.work[l], l + 3) for l in range(1, 6)}
+
+
+def test_estimation_meets_the_criterion_minimally():
+    """bfp-prec-est on level 3: the returned constants meet the rate
+    criterion and one bit less of the inner constant does not."""
+    r = est.bfp_prec_est(2, 3, 16, 1.05)
+    rate = lambda q_c, q_i: est.conv_rate_v_cycle(2, 3, est.width_rules(3, q_c, q_i))
+    assert r["rho"] / r["rho_ref"] < 1.05
+    assert r["rho_ref"] == pytest.approx(rate(16, 16))
+    if r["q_inner"] > 1:
+        assert rate(r["q_check"], r["q_inner"] - 1) / r["rho_ref"] >= 1.05
+    # the check width does not matter here: A is exact and b = 0
+    assert r["q_check"] == 1

@@ -1,0 +1,29 @@
+"""The device-driven a priori precision estimation (Section 6.2) against the
+oracle's: the error propagation matrices agree value for value (the BFP
+V-cycles are bit-exact), and so do the estimated constants."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import estimate as oest
+from oracle import mg
+from paper_2307_00124_amd import estimate as est
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("ndim,j,qc,qi", [(2, 3, 30, 30), (2, 3, 1, 4), (2, 4, 2, 6), (3, 2, 1, 3)])
+def test_error_propagation_matches_oracle(ndim, j, qc, qi):
+    wd = est.width_rules(j, qc, qi)
+    E = est.error_propagation(ndim, j, wd)
+    Eo = oest.error_propagation(ndim, j, mg.Widths(*wd))
+    assert np.array_equal(E, Eo)
+    assert np.array_equal(est.dense_A(j, ndim), oest.dense_A(j, ndim))
+
+
+def test_estimation_matches_oracle():
+    r = est.bfp_prec_est(2, 3, 16, 1.05)
+    ro = oest.bfp_prec_est(2, 3, 16, 1.05)
+    assert (r["q_check"], r["q_inner"]) == (ro["q_check"], ro["q_inner"])
+    assert r["rho"] == pytest.approx(ro["rho"], rel=1e-12)

@@ -188,6 +188,10 @@ def main():
     bytes_after, launches_after = H.counters()
     step_bytes = bytes_after - bytes_before
     step_launches = launches_after - launches_before
+    # the solve's hierarchy (and the second stream mg_fmg_f64 created for it,
+    # which holds one of HIP's hardware queues) is not needed by the later legs
+    del H, x, b, r, xout
+    torch.cuda.empty_cache()
 
     # ------------------------------------- FP64 multigrid comparator ---
     fp64 = bench_fp64(P, torch, f, L, us, h2, disc, stream, ev)
@@ -253,6 +257,7 @@ def main():
     # ----------------------------------------- solve diagnostics -------
     diagnostics = bench_diag(P, torch, f, L, timed, stream)
     diagnostics["ir_fallback"] = bench_fallback(P, W, torch, dev, stream, ev)
+    estimation = bench_estimate(torch)
 
     # --------------------------------------------------- batched solves ---
     batch = None
@@ -325,6 +330,7 @@ def main():
         "c1_33x33": c1,
         "sweep": sweep,
         "diagnostics": diagnostics,
+        "precision_estimation": estimation,
         "batched": batch,
         "serving": serving,
         "cpu_baseline": cpu,
@@ -580,6 +586,23 @@ def bench_fallback(P, W, torch, dev, stream, ev, L=10, iters=12):
         del H
     torch.cuda.empty_cache()
     return out
+
+
+def bench_estimate(torch, j_c=5, q_max=27, rho_thresh=1.05):
+    """Algorithm bfp-prec-est (Section 6.2) on the 33 x 33 level with the
+    paper's j_c = 5 and rho_thresh = 1.05 (q_max = 27: every width is
+    capped at 32 bits here), its V-cycles on the device."""
+    from paper_2307_00124_amd import estimate as est
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = est.bfp_prec_est(2, j_c, q_max, rho_thresh)
+    torch.cuda.synchronize()
+    r = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+    r.update({"what": "bfp-prec-est on level %d (%d basis vectors), q_max = %d, rho_thresh = %.2f; "
+                      "check width rule 3j + q_check, inner width rule j + q_inner" %
+                      (j_c, ((1 << j_c) - 1) ** 2, q_max, rho_thresh),
+              "seconds": round(time.perf_counter() - t0, 2)})
+    return r
 
 
 def bench_c1(P, W, torch, dev, stream, ev):

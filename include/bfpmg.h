@@ -309,6 +309,9 @@ int mg_fmg(mg_hierarchy* h, void* stream);
  * priority) while the program runs; that stream starts after the work
  * issued on `stream` so far, and `stream` waits for it before the finer
  * levels' FMG, so the call is ordered on `stream` like the others.
+ * The second stream lives as long as the hierarchy and, like any HIP
+ * stream, takes one of the process's hardware queues (GPU_MAX_HW_QUEUES):
+ * destroy hierarchies that are done with to leave queues to other streams.
  * rhs_dev is read during the call only. Errors: BFP_EINVAL for a NULL
  * argument or level pointer (nothing issued), BFP_EHIP if the stream or
  * events cannot be created.                                              */

@@ -259,15 +259,19 @@ static void fill_common(OpArgs* op, int w_out, const bfp_vec* x, const bfp_vec* 
 // Run one op in the requested mode: nnqcomp in one launch, qcomp as the
 // mu* pass followed by the output pass.
 template <typename L, typename F>
-static int run_modes(L& launch, int mode, F&& go) {
+static int run_modes(L& launch, int mode, hipStream_t s, F&& go) {
   if (g_rec) return record(launch, mode == BFP_SATURATE ? kModeSat : kExModeQ);
+  int rc;
   if (mode == BFP_SATURATE) {
     launch.op.mode = kModeSat;
-    return hip_check(go(launch), "kernel launch");
+    if ((rc = hip_check(go(launch), "kernel launch"))) return rc;
+    if (launch.op.diag)
+      rc = hip_check(launch_diag_sat(launch.op.diag, launch.op.z_meta, s), "diagnostics");
+    return rc;
   }
   launch.op.mode = kModeQ1;
-  int rc = hip_check(go(launch), "kernel launch (qcomp pass 1)");
-  if (rc) return rc;
+  if ((rc = hip_check(go(launch), "kernel launch (qcomp pass 1)"))) return rc;
+  if (launch.op.diag && (rc = hip_check(launch_diag_q(launch.op, s), "diagnostics"))) return rc;
   launch.op.mode = kModeQ2;
   return hip_check(go(launch), "kernel launch (qcomp pass 2)");
 }
@@ -362,7 +366,7 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
       const int64_t segs = (x->n + 1 + 255) / 256;
       L.wx = segs >= 4 ? 4 : (segs >= 2 ? 2 : 1);
     }
-    return run_modes(L, mode, [&](StarLaunch& l) { return launch_star(l, s); });
+    return run_modes(L, mode, s, [&](StarLaunch& l) { return launch_star(l, s); });
   }
   if (A->kind == BFP_STENCIL_R || A->kind == BFP_STENCIL_P) {
     const bfp_vec* fine = A->kind == BFP_STENCIL_R ? x : z;
@@ -386,7 +390,7 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
     L.xbits = x->storage_bits;
     L.ybits = y ? y->storage_bits : 32;
     L.zbits = z->storage_bits;
-    return run_modes(L, mode, [&](TransferLaunch& l) { return launch_transfer(l, s); });
+    return run_modes(L, mode, s, [&](TransferLaunch& l) { return launch_transfer(l, s); });
   }
   return fail(BFP_EINVAL, "unknown stencil kind %d", A->kind);
 }
@@ -430,7 +434,7 @@ int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta
   }
   if (mode != BFP_NORMALIZE && mode != BFP_SATURATE) return fail(BFP_EINVAL, "bad mode %d", mode);
   if ((rc = fill_gamma(gamma, mode, &L.op.g))) return rc;
-  return run_modes(L, mode, [&](PointLaunch& l) { return launch_point(l, s); });
+  return run_modes(L, mode, s, [&](PointLaunch& l) { return launch_point(l, s); });
 }
 
 }  // namespace bfpk

@@ -265,12 +265,9 @@ __device__ __forceinline__ void diag_count(int64_t* diag, int dbin, int dsat, in
 }
 
 // Reduce the per-thread (max, min, saturations) of a block's outputs; the
-// last block publishes exponent / max / min / saturation count (and the
-// op's diagnostic counts when `diag` is set).
+// last block publishes exponent / max / min / saturation count.
 __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64_t tsat,
-                                               int64_t* zm, int64_t e_out,
-                                               int64_t* diag = nullptr, int dbin = -1,
-                                               int dsat = 0) {
+                                               int64_t* zm, int64_t e_out) {
   __shared__ int64_t s_red[3][kBlock / 64];
   const int tid = threadIdx.x;
   tmax = wave_max(tmax);
@@ -294,7 +291,6 @@ __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64
       zm[kMetaMin] = bmin;
       zm[kMetaSat] = bsat;
       zm[kMetaExp] = e_out;
-      diag_count(diag, dbin, dsat, bsat);
       return;
     }
     int64_t* set = acc_set(zm);
@@ -315,7 +311,6 @@ __device__ __forceinline__ void finish_outputs(int64_t tmax, int64_t tmin, int64
       zm[kMetaMin] = mn;
       zm[kMetaSat] = st;
       zm[kMetaExp] = e_out;
-      diag_count(diag, dbin, dsat, st);
     }
   }
 }

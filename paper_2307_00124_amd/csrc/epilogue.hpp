@@ -105,9 +105,11 @@ __device__ __forceinline__ void with_fast(const E& e, F&& body) {
   else body(std::integral_constant<int, kVarGen>());
 }
 
-// DG = false compiles the diagnostic counting out (the executor's plain
-// programs); launched kernels keep it behind a null check.
-template <int PASS, bool HASY, bool DG = true>
+// DG = true: the executor's programs that count diagnostics (the op's
+// counts are prepared at set-up). Launched operations are counted by small
+// kernels of their own (k_diag_q, k_diag_sat), so these carry no
+// diagnostic state at all.
+template <int PASS, bool HASY, bool DG = false>
 struct Epi {
   Resolved R;
   int64_t alpha_m, beta_m, lo, hi;
@@ -244,8 +246,9 @@ struct Epi {
 
   __device__ __forceinline__ void finish() {
     if (PASS == kQ1) finish_mu(tmu, zm);
-    else finish_outputs(tmax, tmin, tsat, zm, R.eo, diag, dbin, dsat);
+    else finish_outputs(tmax, tmin, tsat, zm, R.eo);
   }
+
 };
 
 // Storage-type dispatch helpers (host side).

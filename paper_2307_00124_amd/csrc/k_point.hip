@@ -321,6 +321,34 @@ __global__ __launch_bounds__(kBlock) void k_dot(const DotLaunch L) {
   }
 }
 
+// Diagnostics of a launched operation (one thread each). Between the two
+// qcomp passes, mu* (from the first) and the estimate's metadata (not yet
+// changed by the second) give the window gap of the call; after an nnqcomp
+// call, the output's saturation count.
+__global__ void k_diag_q(const OpArgs op) {
+  const Resolved r = resolve(op, ptr_meta(op));
+  bool zero;
+  const int64_t nu = gamma_nu(op.g, ptr_meta(op), &zero);
+  // mu* = eo - ez + w_out in the second pass
+  if (!zero) diag_count(op.diag, diag_gap_bin(nu - r.ez - (r.eo - r.ez + op.w_out)), 0, 0);
+}
+
+__global__ void k_diag_sat(int64_t* diag, const int64_t* zm) {
+  diag_count(diag, -1, 1, zm[kMetaSat]);
+}
+
+hipError_t launch_diag_q(const OpArgs& op, hipStream_t s) {
+  OpArgs o = op;
+  o.mode = kModeQ2;
+  hipLaunchKernelGGL(k_diag_q, dim3(1), dim3(1), 0, s, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_sat(int64_t* diag, const int64_t* zm, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_sat, dim3(1), dim3(1), 0, s, diag, zm);
+  return hipGetLastError();
+}
+
 hipError_t launch_dot(const DotLaunch& L, hipStream_t s) {
   const unsigned blocks = grid_for(row_items(L.n, L.ndim));
   return with_type(L.xbits, [&](auto tx) {

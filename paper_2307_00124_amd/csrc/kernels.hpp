@@ -62,6 +62,12 @@ struct PointLaunch {
 };
 hipError_t launch_point(const PointLaunch& L, hipStream_t s);
 
+// Diagnostics of a launched operation with op.diag set: the qcomp window
+// gap (launched between the two passes) or the nnqcomp saturations
+// (launched after the operation, reading its output metadata zm).
+hipError_t launch_diag_q(const OpArgs& op, hipStream_t s);
+hipError_t launch_diag_sat(int64_t* diag, const int64_t* zm, hipStream_t s);
+
 // FP64 <-> BFP conversion, initialisation and the exact dot product.
 struct ConvertLaunch {
   const double* src;   // dense (n+2)^ndim

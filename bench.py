@@ -596,10 +596,17 @@ def bench_estimate(torch, j_c=5, q_max=27, rho_thresh=1.05):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = est.bfp_prec_est(2, j_c, q_max, rho_thresh)
+    # the smoother parameter by the same machinery (eta = i / 100 minimizing
+    # rho_v, widths at the cap), for the two cycle shapes the solves use
+    wide = est.width_rules(j_c, q_max, q_max)
+    for name, nu in (("eta_v10", (1, 0)), ("eta_v22", (2, 2))):
+        i, rho = est.estimate_eta(2, j_c, wide, nu=nu)
+        r[name] = {"percent": i, "rho_v": round(rho, 6)}
     torch.cuda.synchronize()
     r = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
     r.update({"what": "bfp-prec-est on level %d (%d basis vectors), q_max = %d, rho_thresh = %.2f; "
-                      "check width rule 3j + q_check, inner width rule j + q_inner" %
+                      "check width rule 3j + q_check, inner width rule j + q_inner; and the "
+                      "Chebyshev parameter eta minimizing rho_v for V(1,0) and V(2,2)" %
                       (j_c, ((1 << j_c) - 1) ** 2, q_max, rho_thresh),
               "seconds": round(time.perf_counter() - t0, 2)})
     return r

@@ -102,3 +102,33 @@ def bfp_prec_est(ndim: int, j_c: int, q_max: int, rho_thresh: float, rate=None,
     q_inner = _min_q(lambda q: rate(width_rules(j_c, q_check, q)) / ref < rho_thresh, q_max)
     return {"rho_ref": ref, "q_check": q_check, "q_inner": q_inner,
             "rho": rate(width_rules(j_c, q_check, q_inner))}
+
+
+def argmin_unimodal(f, lo: int, hi: int) -> int:
+    """Smallest minimizer of f over the integers lo..hi, by ternary search
+    (f taken as unimodal there), evaluating f at most once per point."""
+    cache = {}
+
+    def F(i):
+        if i not in cache:
+            cache[i] = f(i)
+        return cache[i]
+
+    while hi - lo > 2:
+        m1 = lo + (hi - lo) // 3
+        m2 = hi - (hi - lo) // 3
+        if F(m1) <= F(m2):
+            hi = m2
+        else:
+            lo = m1
+    return min(range(lo, hi + 1), key=lambda i: (F(i), i))
+
+
+def estimate_eta(ndim: int, j: int, widths: mg.Widths, nu=(1, 0), lo: int = 1, hi: int = 99,
+                 **kw) -> tuple[int, float]:
+    """The Chebyshev smoother's parameter eta = i / 100 with the smallest
+    V-cycle rate rho_v on level j (the same machinery as bfp-prec-est, for
+    the eta the paper fixes empirically); returns (i, rho_v)."""
+    rate = lambda i: conv_rate_v_cycle(ndim, j, widths, nu=nu, eta=Fraction(i, 100), **kw)
+    i = argmin_unimodal(rate, lo, hi)
+    return i, rate(i)

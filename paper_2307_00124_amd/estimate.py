@@ -114,3 +114,34 @@ def bfp_prec_est(ndim: int, j_c: int, q_max: int, rho_thresh: float, **kw) -> di
     q_inner = _min_q(lambda q: rate(q_check, q) / ref < rho_thresh, q_max)
     return {"rho_ref": ref, "q_check": q_check, "q_inner": q_inner,
             "rho": rate(q_check, q_inner), "rates_evaluated": len(cache)}
+
+
+def argmin_unimodal(f, lo: int, hi: int) -> int:
+    """Smallest minimizer of f over the integers lo..hi, by ternary search
+    (f taken as unimodal there), evaluating f at most once per point."""
+    cache = {}
+
+    def F(i):
+        if i not in cache:
+            cache[i] = f(i)
+        return cache[i]
+
+    while hi - lo > 2:
+        m1 = lo + (hi - lo) // 3
+        m2 = hi - (hi - lo) // 3
+        if F(m1) <= F(m2):
+            hi = m2
+        else:
+            lo = m1
+    return min(range(lo, hi + 1), key=lambda i: (F(i), i))
+
+
+def estimate_eta(ndim: int, j: int, widths, nu=(1, 0), lo: int = 1, hi: int = 99,
+                 **kw) -> tuple[int, float]:
+    """The Chebyshev smoother's parameter eta = i / 100 (the library's
+    integer percent) with the smallest V-cycle rate rho_v on level j: the
+    bfp-prec-est machinery applied to the eta the paper fixes empirically.
+    Returns (i, rho_v)."""
+    rate = lambda i: conv_rate_v_cycle(ndim, j, widths, nu=nu, eta=i, **kw)
+    i = argmin_unimodal(rate, lo, hi)
+    return i, rate(i)

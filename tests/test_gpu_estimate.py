@@ -27,3 +27,10 @@ def test_estimation_matches_oracle():
     ro = oest.bfp_prec_est(2, 3, 16, 1.05)
     assert (r["q_check"], r["q_inner"]) == (ro["q_check"], ro["q_inner"])
     assert r["rho"] == pytest.approx(ro["rho"], rel=1e-12)
+
+
+def test_eta_estimate_matches_oracle():
+    wd = est.width_rules(3, 16, 16)
+    i, rho = est.estimate_eta(2, 3, wd, lo=10, hi=40)
+    io, rho_o = oest.estimate_eta(2, 3, mg.Widths(*wd), lo=10, hi=40)
+    assert i == io and rho == pytest.approx(rho_o, rel=1e-12)

@@ -67,3 +67,19 @@ def test_estimation_meets_the_criterion_minimally():
         assert rate(r["q_check"], r["q_inner"] - 1) / r["rho_ref"] >= 1.05
     # the check width does not matter here: A is exact and b = 0
     assert r["q_check"] == 1
+
+
+def test_argmin_unimodal():
+    f = lambda i: (i - 37) ** 2
+    assert est.argmin_unimodal(f, 1, 99) == 37
+    assert est.argmin_unimodal(lambda i: abs(i - 5) // 2, 1, 20) == 4   # ties: the smallest
+
+
+def test_eta_search_finds_the_exhaustive_minimum():
+    """On level 3 the rate is unimodal in eta over 15..35 %: the ternary
+    search returns the exhaustive argmin."""
+    wd = est.width_rules(3, 16, 16)
+    i, rho = est.estimate_eta(2, 3, wd, lo=15, hi=35)
+    rates = {k: est.conv_rate_v_cycle(2, 3, wd, eta=Fraction(k, 100)) for k in range(15, 36)}
+    best = min(rates, key=lambda k: (rates[k], k))
+    assert i == best and rho == pytest.approx(rates[best])

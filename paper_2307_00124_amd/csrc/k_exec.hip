@@ -149,10 +149,75 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY, DG>& E, MetaRow&
 // Points are enumerated on a 2^lg >= n padded index space; a padding slot
 // becomes the interior point (1, 1, 1), which keeps every address in bounds,
 // and is neither stored nor counted.
+__device__ __forceinline__ OpArgs with_mode(const OpArgs& a, int mode) {
+  OpArgs op = a;
+  op.mode = mode;
+  return op;
+}
+
+// PASS = kQF: both qcomp passes of one op. When every output point fits
+// one round (U points per thread) the exact values are gathered once, kept
+// in registers across the mu* reduction and quantized from there (the same
+// values the second pass would gather again: the first stores nothing);
+// otherwise the two passes run one after the other.
+constexpr int kQF = 3;
+
 template <int NT, int ND, int PASS, bool HASY, bool DG, int U, typename Gather>
 __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uintptr_t base,
                                         int n, const void* yp, int ybits, int64_t py, void* zp0,
                                         int zbits, int64_t pz, Gather&& gather) {
+  if constexpr (PASS == kQF) {
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;
+    const int tot = ND == 3 ? 1 << (3 * lg) : 1 << (2 * lg);
+    const OpArgs q1 = with_mode(op, kModeQ1), q2 = with_mode(op, kModeQ2);
+    if (tot > U * NT) {
+      ex_loop<NT, ND, kQ1, HASY, DG, U>(q1, ma, base, n, yp, ybits, py, zp0, zbits, pz, gather);
+      ex_loop<NT, ND, kOut, HASY, DG, U>(q2, ma, base, n, yp, ybits, py, zp0, zbits, pz, gather);
+      return;
+    }
+    const int M = (1 << lg) - 1;
+    const int64_t side = n + 2;
+    const Src ys = src_of(yp, ybits, base);
+    void* zp = rel(zp0, base);
+    Epi<kQ1, HASY, DG> E1;
+    E1.init(q1, ma);
+    int64_t g[U], zo[U];
+    int32_t yv[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = threadIdx.x + u * NT;
+      int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
+      ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
+      if (!ok[u]) {
+        x = 1;
+        y = 1;
+        z = ND == 3 ? 1 : 0;
+      }
+      const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
+      g[u] = gather(z, y, x);
+      zo[u] = row * pz + x;
+      yv[u] = HASY ? ldx(ys, row * py + x) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) E1.template put<kVarGen>(g[u], yv[u], ok[u]);
+    ex_finish<NT>(E1, ma.lm[ma.s[kOpZ]], *ma.pend);   // mu*, then a barrier
+    Epi<kOut, HASY, DG> E2;
+    E2.init(q2, ma);
+    auto store = [&](auto var_tag) {
+      constexpr int VAR = decltype(var_tag)::value;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t v = E2.template put<VAR>(g[u], yv[u], ok[u]);
+        if (ok[u]) stv(zp, zbits, zo[u], v);
+      }
+    };
+    if (E2.fast) store(std::integral_constant<int, kVarFast>());
+    else store(std::integral_constant<int, kVarGen>());
+    ex_finish<NT>(E2, ma.lm[ma.s[kOpZ]], *ma.pend);
+    return;
+  } else {
   Epi<PASS, HASY, DG> E;
   E.init(op, ma);
   const Src ys = src_of(yp, ybits, base);
@@ -194,6 +259,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   if (PASS != kQ1 && E.fast) body(std::integral_constant<int, kVarFast>());
   else body(std::integral_constant<int, kVarGen>());
   ex_finish<NT>(E, ma.lm[ma.s[kOpZ]], *ma.pend);
+  }
 }
 
 template <int NT, int ND, int PASS, bool HASY, bool DG>
@@ -311,11 +377,6 @@ __device__ __forceinline__ void ex_zero(const ZeroOp& Z, int64_t* zm, uintptr_t 
     zm[threadIdx.x] = threadIdx.x == kMetaExp ? Z.exp : (threadIdx.x == kMetaMu ? 1 : 0);
 }
 
-__device__ __forceinline__ OpArgs with_mode(const OpArgs& a, int mode) {
-  OpArgs op = a;
-  op.mode = mode;
-  return op;
-}
 
 template <int NT, int ND, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, PendingDiag* pend,
@@ -465,13 +526,8 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
                                           : (op.kind == kExPoint ? op.u.pt.op.has_y
                                                                  : op.u.tr.op.has_y);
       if (op.mode == kExModeQ) {
-        if (hasy) {
-          ex_dispatch<NT, ND, kQ1, true, DG>(op, lm, &pend, kModeQ1, base);
-          ex_dispatch<NT, ND, kOut, true, DG>(op, lm, &pend, kModeQ2, base);
-        } else {
-          ex_dispatch<NT, ND, kQ1, false, DG>(op, lm, &pend, kModeQ1, base);
-          ex_dispatch<NT, ND, kOut, false, DG>(op, lm, &pend, kModeQ2, base);
-        }
+        if (hasy) ex_dispatch<NT, ND, kQF, true, DG>(op, lm, &pend, kModeQ2, base);
+        else ex_dispatch<NT, ND, kQF, false, DG>(op, lm, &pend, kModeQ2, base);
       } else if (hasy) {
         ex_dispatch<NT, ND, kOut, true, DG>(op, lm, &pend, op.mode, base);
       } else {

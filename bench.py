@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--loop-sample", type=int, default=32,
                     help="problems solved one at a time for the batched comparison")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the diagnostics, fallback and precision-estimation legs")
     ap.add_argument("--level3d", type=int, default=9, help="3D solve level (0: skip)")
     ap.add_argument("--serve", type=int, default=2000,
                     help="requests of the serving trace (0: skip)")
@@ -255,9 +257,11 @@ def main():
         torch.cuda.empty_cache()
 
     # ----------------------------------------- solve diagnostics -------
-    diagnostics = bench_diag(P, torch, f, L, timed, stream)
-    diagnostics["ir_fallback"] = bench_fallback(P, W, torch, dev, stream, ev)
-    estimation = bench_estimate(torch)
+    diagnostics = estimation = None
+    if not args.no_extras:
+        diagnostics = bench_diag(P, torch, f, L, timed, stream)
+        diagnostics["ir_fallback"] = bench_fallback(P, W, torch, dev, stream, ev)
+        estimation = bench_estimate(torch)
 
     # --------------------------------------------------- batched solves ---
     batch = None

@@ -190,6 +190,20 @@ def main():
     bytes_after, launches_after = H.counters()
     step_bytes = bytes_after - bytes_before
     step_launches = launches_after - launches_before
+    # the same step without the FP64 -> BFP quantization of the right-hand
+    # sides (b_j already set): FMG, normalized solution, exact r.r
+    for _ in range(2):
+        H.fmg(stream)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(args.steps):
+        H.fmg(stream)
+        P.bfp_normalize(H.get_vec(L, 0), H.get_vec(L, 0).w, xout, stream)
+        P.bfp_dot(H.get_vec(L, 2), H.get_vec(L, 2), dot_out, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_no_conv = e0.elapsed_time(e1) / args.steps
     # the solve's hierarchy (and the second stream mg_fmg_f64 created for it,
     # which holds one of HIP's hardware queues) is not needed by the later legs
     del H, x, b, r, xout
@@ -309,6 +323,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_without_rhs_quantization": round(ms_no_conv, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

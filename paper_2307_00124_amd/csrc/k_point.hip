@@ -31,19 +31,33 @@ __global__ __launch_bounds__(kBlock) void k_point(const PointLaunch L) {
   TZ* Z = static_cast<TZ*>(L.z);
   Epi<PASS, HASY> E;
   E.init(L.op);
+  // kPU items per round, their loads issued before any of them is used (a
+  // round keeps kPU times the bytes of one item in flight)
+  constexpr int kPU = 4;
   with_fast(E, [&](auto fast_tag) {
     constexpr int VAR = decltype(fast_tag)::value;
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-      const int64_t rr = interior_row(it / nchunk, n, L.ndim);
-      const int64_t c = (it % nchunk) * 1024 + threadIdx.x * 4;
-      if (c >= n + 2) continue;
-      int32_t xv[4], yv[4] = {0, 0, 0, 0};
-      ld4(X, rr * L.px + c, xv, true);
-      if (HASY) ld4(Y, rr * L.py + c, yv, true);
-      int64_t out[4];
+    for (int64_t it0 = blockIdx.x; it0 < items; it0 += (int64_t)kPU * gridDim.x) {
+      int32_t xv[kPU][4], yv[kPU][4];
+      int64_t rr[kPU], c[kPU];
+      bool live[kPU];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) out[k] = E.template put<VAR>(xv[k], yv[k], true);
-      if (PASS != kQ1) st4(Z, rr * L.pz + c, out);
+      for (int u = 0; u < kPU; ++u) {
+        const int64_t it = it0 + (int64_t)u * gridDim.x;
+        rr[u] = interior_row((it < items ? it : 0) / nchunk, n, L.ndim);
+        c[u] = ((it < items ? it : 0) % nchunk) * 1024 + threadIdx.x * 4;
+        live[u] = it < items && c[u] < n + 2;
+        ld4(X, rr[u] * L.px + c[u], xv[u], live[u]);
+        if (HASY) ld4(Y, rr[u] * L.py + c[u], yv[u], live[u]);
+        else yv[u][0] = yv[u][1] = yv[u][2] = yv[u][3] = 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kPU; ++u) {
+        if (!live[u]) continue;
+        int64_t out[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[k] = E.template put<VAR>(xv[u][k], yv[u][k], true);
+        if (PASS != kQ1) st4(Z, rr[u] * L.pz + c[u], out);
+      }
     }
   });
   E.finish();

@@ -10,11 +10,24 @@
 
 #include "epilogue.hpp"
 
+#include <utility>
+
 namespace bfpk {
 
 template <int ND>
 __device__ __forceinline__ int tap_index(const int (&o)[3]) {
   return ND == 2 ? (o[1] + 1) * 3 + (o[2] + 1) : ((o[0] + 1) * 3 + (o[1] + 1)) * 3 + (o[2] + 1);
+}
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): a loop
+// whose index is a compile-time constant from the start
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>());
 }
 
 // one coarse output point per thread; work items: (output row, run of 256 points) pairs, grid-strided over at
@@ -38,18 +51,22 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const TransferLaunch L) {
     int64_t zc = 0, yc;
     if (ND == 3) { zc = row / nc + 1; yc = row % nc + 1; } else { yc = row + 1; }
     if (xc > nc) continue;
+    // all 3^ND loads of the point are issued together (compile-time offsets
+    // and taps), not one fine row after the other
     int64_t g = 0;
-    int o[3];
-    for (o[0] = (ND == 3 ? -1 : 0); o[0] <= (ND == 3 ? 1 : 0); ++o[0])
-      for (o[1] = -1; o[1] <= 1; ++o[1]) {
-        const int64_t frow = ND == 3 ? (2 * zc + o[0]) * sf + (2 * yc + o[1]) : (2 * yc + o[1]);
+    static_for<ND == 3 ? 3 : 1>([&](auto iz_) {
+      constexpr int oz = ND == 3 ? decltype(iz_)::value - 1 : 0;
+      static_for<3>([&](auto iy_) {
+        constexpr int oy = decltype(iy_)::value - 1;
+        const int64_t frow = ND == 3 ? (2 * zc + oz) * sf + (2 * yc + oy) : (2 * yc + oy);
         const TX* xr = X + frow * L.px + 2 * xc;
-#pragma unroll
-        for (int ox = -1; ox <= 1; ++ox) {
-          o[2] = ox;
-          g += (int64_t)L.taps[tap_index<ND>(o)] * (int64_t)xr[ox];
-        }
-      }
+        static_for<3>([&](auto ix_) {
+          constexpr int ox = decltype(ix_)::value - 1;
+          constexpr int ti = ND == 2 ? (oy + 1) * 3 + (ox + 1) : ((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1);
+          g += (int64_t)L.taps[ti] * (int64_t)xr[ox];
+        });
+      });
+    });
     const int64_t crow = ND == 3 ? zc * sc + yc : yc;
     const int64_t yv = HASY ? (int64_t)Y[crow * L.py + xc] : 0;
     const int64_t v = E.template put<VAR>(g, yv, true);

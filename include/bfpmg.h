@@ -460,13 +460,18 @@ int mg_server_destroy(mg_server* s);
  * "star2d_rows" / "star3d_rows" = rows or planes one wave of the star
  * stencil kernels marches on large grids, "star2d_small_n" /
  * "star3d_small_n" = grid size below which every wave takes a single row
- * (values >= 1); "exec_max_points" = largest grid (in interior points) whose
+ * (values >= 1; "star2d_rows" = 0 restores the default, rows = n^2 / 2^18
+ * rounded down to a power of two in [1, 64]); "exec_max_points" = largest grid (in interior points) whose
  * level runs inside the one-workgroup coarse-level programs a hierarchy
  * records at creation (0 = never; read by mg_hierarchy_bytes/create);
  * "diagnostics" = 1: hierarchies created while it is set keep the solve
  * diagnostics of mg_diag_read (0, the default: none, and no cost; read by
  * mg_hierarchy_bytes/create, which must see the same value).              */
 int bfp_tuning_set(const char* key, int value);
+
+/* Current value of a tuning key (the keys of bfp_tuning_set) into *value.
+ * BFP_EINVAL for an unknown key or a NULL argument.                      */
+int bfp_tuning_get(const char* key, int* value);
 
 /* Human-readable description of the last error on this thread.           */
 const char* bfp_last_error(void);

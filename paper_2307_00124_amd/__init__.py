@@ -275,6 +275,12 @@ def bfp_tuning_set(key: str, value: int) -> None:
     check(lib.bfp_tuning_set(key.encode(), int(value)), "bfp_tuning_set")
 
 
+def bfp_tuning_get(key: str) -> int:
+    v = C.c_int(0)
+    check(lib.bfp_tuning_get(key.encode(), C.byref(v)), "bfp_tuning_get")
+    return int(v.value)
+
+
 def bfp_cheby_coeffs(rho: tuple[int, int], eta: tuple[int, int], scale: tuple[int, int] = (1, 1),
                      w: int = 16) -> tuple[abi.bfp_scalar, abi.bfp_scalar]:
     c1, c2 = abi.bfp_scalar(), abi.bfp_scalar()

@@ -123,6 +123,7 @@ SIGNATURES = {
     "mg_server_collect": (I, [VP, P(C.c_uint64), P(mg_result), I, P(I)]),
     "mg_server_destroy": (I, [VP]),
     "bfp_tuning_set": (I, [C.c_char_p, I]),
+    "bfp_tuning_get": (I, [C.c_char_p, C.POINTER(I)]),
     "bfp_last_error": (C.c_char_p, []),
 }
 

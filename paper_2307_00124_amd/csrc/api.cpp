@@ -593,11 +593,25 @@ int bfp_tuning_set(const char* key, int value) {
     g_diagnostics = value;
     return BFP_OK;
   }
+  // 2D: rows 0 restores the size heuristic (then small_n is not read)
+  if (k == "star2d_rows") { g_star2d_rows_large = value; return BFP_OK; }
+  if (k == "star2d_small_n") { g_star2d_small_n = value; return BFP_OK; }
   if (value < 1) return fail(BFP_EINVAL, "value out of range");
-  if (k == "star2d_rows") g_star2d_rows_large = value;
-  else if (k == "star2d_small_n") g_star2d_small_n = value;
-  else if (k == "star3d_rows") g_star3d_rows_large = value;
+  if (k == "star3d_rows") g_star3d_rows_large = value;
   else if (k == "star3d_small_n") g_star3d_small_n = value;
+  else return fail(BFP_EINVAL, "unknown tuning key %s", key);
+  return BFP_OK;
+}
+
+int bfp_tuning_get(const char* key, int* value) {
+  if (!key || !value) return fail(BFP_EINVAL, "NULL argument");
+  const std::string k(key);
+  if (k == "exec_max_points") *value = g_exec_max_points;
+  else if (k == "diagnostics") *value = g_diagnostics;
+  else if (k == "star2d_rows") *value = g_star2d_rows_large;
+  else if (k == "star2d_small_n") *value = g_star2d_small_n;
+  else if (k == "star3d_rows") *value = g_star3d_rows_large;
+  else if (k == "star3d_small_n") *value = g_star3d_small_n;
   else return fail(BFP_EINVAL, "unknown tuning key %s", key);
   return BFP_OK;
 }

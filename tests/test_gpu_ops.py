@@ -113,34 +113,43 @@ def test_from_f64_zero_and_nonfinite():
 STORAGE = [(32, 32, 32), (16, 32, 8), (8, 16, 16), (32, 8, 16)]
 
 
+def star_case(g, ndim, n, mode, with_y, case, what=""):
+    """One alpha A x + beta y (or alpha A x) call on the device against the
+    oracle: storage combination STORAGE[case], the FD operator (even cases)
+    or a random star with 11-bit taps (odd cases), random widths, exponents
+    and estimate."""
+    bx, by, bz = STORAGE[case]
+    wx = int(g.integers(1, bx + 1))
+    wy = int(g.integers(1, by + 1))
+    wz = int(g.integers(1, bz + 1))
+    Ad, Ao = fd_A(ndim) if case % 2 == 0 else star(ndim, g, int(g.integers(-8, 8)))
+    x = rand_block(g, ndim, n, wx, int(g.integers(-40, 40)))
+    y = rand_block(g, ndim, n, wy, int(g.integers(-40, 40))) if with_y else None
+    al = Scalar(int(g.integers(-(1 << 15), 1 << 15)) or 1, int(g.integers(-10, 10)), 16)
+    be = Scalar(int(g.integers(-(1 << 15), 1 << 15)) or -1, int(g.integers(-10, 10)), 16)
+    if case == 3:
+        al, be = Scalar(1, 0, 2), Scalar(-1, 0, 1)
+    xd = upload(x, bx)
+    yd = upload(y, by) if with_y else None
+    gk = ["explicit", "norm", "sum" if with_y else "norm", "zero"][case]
+    gd, gr = gamma_pair(gk, g, x, xd, y, yd)
+    z = P.Vec(ndim, n, wz, bz)
+    P.bfp_stencil_apply(Ad, xd, P.scalar(al.m, al.e), P.scalar(be.m, be.e), yd, wz, mode,
+                        gd, z)
+    op = blas.gemv(Ao, x, y, al, be) if with_y else blas.spmv(Ao, x)
+    if not with_y:
+        op = blas.Exact(op.e + al.e, op.w + 16, (lambda o=op, a=al: a.m * o.rows()))
+    ref = quantize_ref(op, mode, wz, gr)
+    assert_block_equal(z, ref, f"{what} case {case} storage {(bx, by, bz)} gamma {gk}")
+
+
 @pytest.mark.parametrize("ndim,n", [(2, 1), (2, 7), (2, 37), (2, 300), (3, 1), (3, 5), (3, 19)])
 @pytest.mark.parametrize("mode", [P.BFP_SATURATE, P.BFP_NORMALIZE])
 @pytest.mark.parametrize("with_y", [False, True])
 def test_star_stencil(ndim, n, mode, with_y):
     g = np.random.default_rng(ndim * 1000 + n * 10 + mode * 3 + with_y)
-    for case, (bx, by, bz) in enumerate(STORAGE):
-        wx = int(g.integers(1, bx + 1))
-        wy = int(g.integers(1, by + 1))
-        wz = int(g.integers(1, bz + 1))
-        Ad, Ao = fd_A(ndim) if case % 2 == 0 else star(ndim, g, int(g.integers(-8, 8)))
-        x = rand_block(g, ndim, n, wx, int(g.integers(-40, 40)))
-        y = rand_block(g, ndim, n, wy, int(g.integers(-40, 40))) if with_y else None
-        al = Scalar(int(g.integers(-(1 << 15), 1 << 15)) or 1, int(g.integers(-10, 10)), 16)
-        be = Scalar(int(g.integers(-(1 << 15), 1 << 15)) or -1, int(g.integers(-10, 10)), 16)
-        if case == 3:
-            al, be = Scalar(1, 0, 2), Scalar(-1, 0, 1)
-        xd = upload(x, bx)
-        yd = upload(y, by) if with_y else None
-        gk = ["explicit", "norm", "sum" if with_y else "norm", "zero"][case]
-        gd, gr = gamma_pair(gk, g, x, xd, y, yd)
-        z = P.Vec(ndim, n, wz, bz)
-        P.bfp_stencil_apply(Ad, xd, P.scalar(al.m, al.e), P.scalar(be.m, be.e), yd, wz, mode,
-                            gd, z)
-        op = blas.gemv(Ao, x, y, al, be) if with_y else blas.spmv(Ao, x)
-        if not with_y:
-            op = blas.Exact(op.e + al.e, op.w + 16, (lambda o=op, a=al: a.m * o.rows()))
-        ref = quantize_ref(op, mode, wz, gr)
-        assert_block_equal(z, ref, f"case {case} storage {(bx, by, bz)} gamma {gk}")
+    for case in range(len(STORAGE)):
+        star_case(g, ndim, n, mode, with_y, case)
 
 
 @pytest.mark.parametrize("ndim", [2, 3])

@@ -204,6 +204,7 @@ class Hierarchy:
     nu2: int = 0
     window: bool = True        # qcomp with the Table 1 window (else plain)
     ir_res_saturated: int = 0  # entries the last IR residual saturated
+    trace: list | None = None  # per call: site, level, gamma, exact and output norms
     stats: Stats = field(default_factory=Stats)
     A: dict = field(default_factory=dict)
     R: dict = field(default_factory=dict)
@@ -262,6 +263,13 @@ def _quantize_op(H: Hierarchy, site: str, op: blas.Exact, w_out: int,
     H.stats.add(site, info)
     # diagnostics, on the recursion level of the call
     j = (out.m.shape[0] - 1).bit_length() - 1
+    if H.trace is not None:
+        zm = op.rows()
+        exact = Fraction(max((abs(int(v)) for v in zm.flat), default=0)) * Fraction(2) ** op.e
+        H.trace.append({"site": site, "level": j + 1 if site == "restrict" else j,
+                        "gamma": None if gamma is None else Fraction(gamma),
+                        "exact_norm": exact, "out": out,
+                        "mode": info.mode, "saturated": info.saturated})
     row = H.stats.diag_row(j + 1 if site == "restrict" else j, site)
     if use_q:
         if gamma is not None and gamma > 0:
@@ -273,56 +281,106 @@ def _quantize_op(H: Hierarchy, site: str, op: blas.Exact, w_out: int,
     return out
 
 
-def relax_sweep_from_zero(H: Hierarchy, l: int, r: BFP) -> BFP:
+# One function per call site of Table 1: each forms the exact result of its
+# line of Algorithm IR, V or FMG and quantizes it with that row's estimate.
+
+def relaxation(H: Hierarchy, l: int, r: BFP) -> BFP:
+    """V relaxation y = c2 A r + c1 r (two Chebyshev steps from y = 0);
+    gamma = c1 ||r||, since 0 <= D^-1 A <= 2I bounds ||y|| / ||r|| below c1."""
     s = H.smoother
     return _quantize_op(H, "relax", blas.gemv(H.A[l], r, r, s.c2, s.c1),
                         H.widths.inner[l], s.c1.value * r.norm_inf())
 
 
+def v_residual_gamma(H: Hierarchy, r: BFP) -> Fraction:
+    """(1/4)(2 c1 + 1) ||r||: the bound 2 c1 + 1 on ||A y - r|| / ||r|| after
+    the relaxation, scaled by the empirical 1/4."""
+    return H.smoother.vres * r.norm_inf()
+
+
+def v_residual(H: Hierarchy, l: int, y: BFP, r: BFP, gamma: Fraction) -> BFP:
+    """V residual r_v = A y - r at the inner width (gamma from the caller:
+    v_residual_gamma before the coarse correction, the latest residual of
+    the cycle after it)."""
+    return _quantize_op(H, "v_res", blas.gemv(H.A[l], y, r, ONE, MINUS_ONE),
+                        H.widths.inner[l], gamma)
+
+
+def restriction(H: Hierarchy, l: int, rv: BFP) -> BFP:
+    """Coarse residual R r_v on level l - 1; gamma = ||R|| ||r_v|| (triangle
+    inequality). Its width is the inner width of level l, the recursion
+    level of the call."""
+    return _quantize_op(H, "restrict", blas.spmv(H.R[l], rv), H.widths.inner[l],
+                        H.R[l].norm_inf() * rv.norm_inf())
+
+
+def v_correction(H: Hierarchy, l: int, y: BFP, d: BFP) -> BFP:
+    """y - P d; gamma = ||y|| + ||d|| (nodal interpolation keeps
+    ||P d|| = ||d||, then the triangle inequality)."""
+    return _quantize_op(H, "v_corr", blas.gemv(H.P, d, y, MINUS_ONE, ONE),
+                        H.widths.inner[l], y.norm_inf() + d.norm_inf())
+
+
+def v_update(H: Hierarchy, l: int, y: BFP, z: BFP) -> BFP:
+    """y - z of an added smoothing sweep, with the correction's estimate."""
+    return _quantize_op(H, "v_corr", blas.sub(y, z), H.widths.inner[l],
+                        y.norm_inf() + z.norm_inf())
+
+
+def ir_residual(H: Hierarchy, l: int, x: BFP, gamma: Fraction | None, first: bool,
+                force_q: bool = False) -> BFP:
+    """IR residual A x - b at the inner width; gamma is the norm of the
+    previous residual (the assumption that the residual does not grow)."""
+    r = _quantize_op(H, "ir_res_first" if first else "ir_res",
+                     blas.gemv(H.A[l], x, H.b[l], ONE, MINUS_ONE),
+                     H.widths.inner[l], gamma, force_q=force_q)
+    H.ir_res_saturated = H.stats.last_saturated
+    return r
+
+
+def ir_correction(H: Hierarchy, l: int, x: BFP, y: BFP) -> BFP:
+    """x - y at the working width; gamma = ||x|| + ||y|| (triangle
+    inequality)."""
+    return _quantize_op(H, "ir_corr", blas.sub(x, y), H.widths.work[l],
+                        x.norm_inf() + y.norm_inf())
+
+
+def fmg_prolongation(H: Hierarchy, l: int, x: BFP) -> BFP:
+    """P x_(l-1) at the working width of level l; gamma = ||x|| (nodal
+    interpolation: ||P x|| = ||x||)."""
+    return _quantize_op(H, "fmg_prol", blas.spmv(H.P, x), H.widths.work[l], x.norm_inf())
+
+
+def _sweep(H: Hierarchy, l: int, y: BFP, r: BFP, gamma: Fraction) -> tuple[BFP, BFP]:
+    """One added smoothing sweep: s = A y - r, z = c2 A s + c1 s, y - z."""
+    sres = v_residual(H, l, y, r, gamma)
+    z = relaxation(H, l, sres)
+    return v_update(H, l, y, z), sres
+
+
 def vcycle(H: Hierarchy, l: int, r: BFP) -> BFP:
     """V(nu1, nu2) correction scheme on level l for A y = r (nu1 >= 1)."""
-    w = H.widths.inner[l]
-    s = H.smoother
-    A = H.A[l]
-    y = relax_sweep_from_zero(H, l, r)
+    y = relaxation(H, l, r)
     last_res = None
     for _ in range(1, H.nu1):
-        sres = _quantize_op(H, "v_res", blas.gemv(A, y, r, ONE, MINUS_ONE), w,
-                            s.vres * r.norm_inf())
-        z = _quantize_op(H, "relax", blas.gemv(A, sres, sres, s.c2, s.c1), w,
-                         s.c1.value * sres.norm_inf())
-        y = _quantize_op(H, "v_corr", blas.sub(y, z), w, y.norm_inf() + z.norm_inf())
-        last_res = sres
+        y, last_res = _sweep(H, l, y, r, v_residual_gamma(H, r))
     if l > 1:
-        rv = _quantize_op(H, "v_res", blas.gemv(A, y, r, ONE, MINUS_ONE), w,
-                          s.vres * r.norm_inf())
-        rc = _quantize_op(H, "restrict", blas.spmv(H.R[l], rv), w,
-                          H.R[l].norm_inf() * rv.norm_inf())
-        d = vcycle(H, l - 1, rc)
-        y = _quantize_op(H, "v_corr", blas.gemv(H.P, d, y, MINUS_ONE, ONE), w,
-                         y.norm_inf() + d.norm_inf())
+        rv = v_residual(H, l, y, r, v_residual_gamma(H, r))
+        d = vcycle(H, l - 1, restriction(H, l, rv))
+        y = v_correction(H, l, y, d)
         last_res = rv
     for _ in range(H.nu2):
-        g = last_res.norm_inf() if last_res is not None else s.vres * r.norm_inf()
-        sres = _quantize_op(H, "v_res", blas.gemv(A, y, r, ONE, MINUS_ONE), w, g)
-        z = _quantize_op(H, "relax", blas.gemv(A, sres, sres, s.c2, s.c1), w,
-                         s.c1.value * sres.norm_inf())
-        y = _quantize_op(H, "v_corr", blas.sub(y, z), w, y.norm_inf() + z.norm_inf())
-        last_res = sres
+        g = last_res.norm_inf() if last_res is not None else v_residual_gamma(H, r)
+        y, last_res = _sweep(H, l, y, r, g)
     return y
 
 
 def ir_iteration(H: Hierarchy, l: int, x: BFP, gamma_res: Fraction | None,
                  force_q: bool = False, first: bool = False) -> tuple[BFP, BFP]:
     """One IR-V iteration on level l: returns (new x, the residual)."""
-    r = _quantize_op(H, "ir_res_first" if first else "ir_res",
-                     blas.gemv(H.A[l], x, H.b[l], ONE, MINUS_ONE),
-                     H.widths.inner[l], gamma_res, force_q=force_q)
-    H.ir_res_saturated = H.stats.last_saturated
+    r = ir_residual(H, l, x, gamma_res, first, force_q)
     y = vcycle(H, l, r)
-    xn = _quantize_op(H, "ir_corr", blas.sub(x, y), H.widths.work[l],
-                      x.norm_inf() + y.norm_inf())
-    return xn, r
+    return ir_correction(H, l, x, y), r
 
 
 def fmg(H: Hierarchy, N: int) -> BFP:
@@ -331,8 +389,7 @@ def fmg(H: Hierarchy, N: int) -> BFP:
     r_last = None
     for l in range(1, H.L + 1):
         if l > 1:
-            x = _quantize_op(H, "fmg_prol", blas.spmv(H.P, x), H.widths.work[l],
-                             x.norm_inf())
+            x = fmg_prolongation(H, l, x)
             g_first = r_last.norm_inf()
         else:
             g_first = H.b[1].norm_inf()

@@ -607,26 +607,29 @@ def bench_fallback(P, W, torch, dev, stream, ev, L=10, iters=12):
     return out
 
 
-def bench_estimate(torch, j_c=5, q_max=27, rho_thresh=1.05):
+def bench_estimate(torch, j_c=5, q_max=64, rho_thresh=1.05):
     """Algorithm bfp-prec-est (Section 6.2) on the 33 x 33 level with the
-    paper's j_c = 5 and rho_thresh = 1.05 (q_max = 27: every width is
-    capped at 32 bits here), its V-cycles on the device."""
+    paper's j_c = 5, q_max = 64 and rho_thresh = 1.05, and the scan of the
+    Chebyshev parameter eta = i / 100 minimizing rho_v (Section 5) for the
+    two cycle shapes the solves use; searches, device solves and energy
+    norms all run in the library."""
     from paper_2307_00124_amd import estimate as est
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = est.bfp_prec_est(2, j_c, q_max, rho_thresh)
-    # the smoother parameter by the same machinery (eta = i / 100 minimizing
-    # rho_v, widths at the cap), for the two cycle shapes the solves use
-    wide = est.width_rules(j_c, q_max, q_max)
+    r = est.bfp_prec_est(est.base_params(2, j_c), q_max, rho_thresh)
+    t1 = time.perf_counter()
     for name, nu in (("eta_v10", (1, 0)), ("eta_v22", (2, 2))):
-        i, rho = est.estimate_eta(2, j_c, wide, nu=nu)
-        r[name] = {"percent": i, "rho_v": round(rho, 6)}
+        wide = est.apply_estimate(est.base_params(2, j_c, nu=nu), q_max, q_max)
+        i, rho, rates = est.eta_scan(wide, 1, 99)
+        r[name] = {"percent": i, "rho_v": round(rho, 6),
+                   "rho_v_at_23": round(rates[22], 6), "rho_v_at_13": round(rates[12], 6)}
     torch.cuda.synchronize()
     r = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
     r.update({"what": "bfp-prec-est on level %d (%d basis vectors), q_max = %d, rho_thresh = %.2f; "
-                      "check width rule 3j + q_check, inner width rule j + q_inner; and the "
-                      "Chebyshev parameter eta minimizing rho_v for V(1,0) and V(2,2)" %
+                      "check width rule 3j + q_check, inner width rule j + q_inner (m = 1, k = 2); "
+                      "eta = i / 100, i = 1..99, minimizing rho_v for V(1,0) and V(2,2)" %
                       (j_c, ((1 << j_c) - 1) ** 2, q_max, rho_thresh),
+              "seconds_prec_est": round(t1 - t0, 2),
               "seconds": round(time.perf_counter() - t0, 2)})
     return r
 

@@ -276,6 +276,63 @@ typedef struct {
 int mg_params_init(int ndim, int L, int w, int progressive, int nu1, int nu2, int N,
                    int policy, int eta_percent, mg_params* out);
 
+/* ---- A priori precision estimation (Section 6.2) and eta (Section 5) ----
+ * Host-driven set-up computations on a coarse estimation level j = prm->L
+ * (at most 7 in 2D, 5 in 3D). They run many device solves and synchronize
+ * with the host; they are not steps of a solve.                          */
+
+/* rho_v = ||E||_A for E (host, N x N doubles, column k = E e_k, interior
+ * points ordered x fastest, N = (2^j - 1)^ndim) and the scaled 5- or
+ * 7-point operator A of level j: the square root of the largest
+ * generalized eigenvalue of E^T A E x = lambda A x (conv-rate-v-cycle of
+ * Section 6.2; scaling A does not change it).                            */
+int bfp_energy_norm(const double* E, int ndim, int j, double* rho);
+
+/* Device bytes mg_error_propagation / mg_conv_rate / mg_prec_est /
+ * mg_eta_scan need in their arena for the schedule prm (0 on error).     */
+size_t mg_conv_rate_bytes(const mg_params* prm);
+
+/* E of one IR-V iteration (mg_ir with iters = 1, b = 0) on level prm->L,
+ * built on the device from the canonical basis vectors e_k quantized at
+ * w_work[L] (mantissa 2^(w-2), exponent 2 - w); E_host receives N x N
+ * doubles, column by column. Uses and overwrites the arena; synchronizes
+ * `stream`.                                                               */
+int mg_error_propagation(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
+                         double* E_host);
+
+/* conv-rate-v-cycle: bfp_energy_norm of mg_error_propagation's E.        */
+int mg_conv_rate(const mg_params* prm, void* arena_dev, size_t bytes, void* stream, double* rho);
+
+/* The width rules of Algorithm bfp-prec-est applied to p (levels 1..p->L):
+ * check w_j = j (m + k) + q_check and inner w_j = j m + q_inner (2m = the
+ * order of the PDE, k = the approximation order; 1 and 2 for the FD
+ * Poisson problems), capped at 32 bits, the check width raised to at least
+ * and the inner width lowered to at most the working width p->w_work[j],
+ * which is kept.                                                         */
+int mg_params_apply_estimate(mg_params* p, int q_check, int q_inner, int m, int k);
+
+typedef struct {
+  int32_t q_check, q_inner; /* constants of the check and inner width rules */
+  double rho_ref;           /* rate with both constants at q_max            */
+  double rho;               /* rate with (q_check, q_inner)                 */
+  int32_t rates;            /* distinct width schedules evaluated           */
+} mg_prec_est_result;
+
+/* Algorithm bfp-prec-est on level j_c = base->L: q_check is the smallest q
+ * in 1..q_max (binary search) whose rate, with the inner constant at q_max,
+ * is below rho_thresh times the reference rate; q_inner the smallest with
+ * the check constant q_check. base supplies everything else (working
+ * widths, cycle, policy, Chebyshev coefficients).                        */
+int mg_prec_est(const mg_params* base, int q_max, double rho_thresh, int m, int k,
+                void* arena_dev, size_t bytes, void* stream, mg_prec_est_result* out);
+
+/* The Chebyshev parameter eta = i / 100, i in lo..hi (1 <= lo <= hi <= 99),
+ * with the smallest rate rho_v on level base->L (the minimization of
+ * Section 5, every i evaluated, ties to the smaller i); rates (optional,
+ * hi - lo + 1 doubles) receives every rate.                              */
+int mg_eta_scan(const mg_params* base, int lo, int hi, void* arena_dev, size_t bytes,
+                void* stream, int* eta_percent, double* rho, double* rates);
+
 typedef struct mg_hierarchy mg_hierarchy;
 
 /* Device bytes a hierarchy needs in its arena.                            */

@@ -104,31 +104,15 @@ def bfp_prec_est(ndim: int, j_c: int, q_max: int, rho_thresh: float, rate=None,
             "rho": rate(width_rules(j_c, q_check, q_inner))}
 
 
-def argmin_unimodal(f, lo: int, hi: int) -> int:
-    """Smallest minimizer of f over the integers lo..hi, by ternary search
-    (f taken as unimodal there), evaluating f at most once per point."""
-    cache = {}
-
-    def F(i):
-        if i not in cache:
-            cache[i] = f(i)
-        return cache[i]
-
-    while hi - lo > 2:
-        m1 = lo + (hi - lo) // 3
-        m2 = hi - (hi - lo) // 3
-        if F(m1) <= F(m2):
-            hi = m2
-        else:
-            lo = m1
-    return min(range(lo, hi + 1), key=lambda i: (F(i), i))
-
-
 def estimate_eta(ndim: int, j: int, widths: mg.Widths, nu=(1, 0), lo: int = 1, hi: int = 99,
                  **kw) -> tuple[int, float]:
-    """The Chebyshev smoother's parameter eta = i / 100 with the smallest
-    V-cycle rate rho_v on level j (the same machinery as bfp-prec-est, for
-    the eta the paper fixes empirically); returns (i, rho_v)."""
-    rate = lambda i: conv_rate_v_cycle(ndim, j, widths, nu=nu, eta=Fraction(i, 100), **kw)
-    i = argmin_unimodal(rate, lo, hi)
-    return i, rate(i)
+    """The Chebyshev smoother's parameter: Section 5 minimizes the V-cycle
+    convergence rate over eta = i / 100; every i in lo..hi is evaluated
+    (i = 0 and 100 are excluded since 0 < eta < 1), ties go to the smaller
+    i. Returns (i, rho_v)."""
+    best = None
+    for i in range(lo, hi + 1):
+        r = conv_rate_v_cycle(ndim, j, widths, nu=nu, eta=Fraction(i, 100), **kw)
+        if best is None or r < best[1]:
+            best = (i, r)
+    return best

@@ -57,6 +57,11 @@ class mg_params(C.Structure):
                 ("c1", bfp_scalar), ("c2", bfp_scalar), ("c1_gamma", bfp_scalar)]
 
 
+class mg_prec_est_result(C.Structure):
+    _fields_ = [("q_check", C.c_int32), ("q_inner", C.c_int32), ("rho_ref", C.c_double),
+                ("rho", C.c_double), ("rates", C.c_int32)]
+
+
 class mg_server_cfg(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32),
                 ("exec_max_points", C.c_int32)]
@@ -97,6 +102,15 @@ SIGNATURES = {
     "bfp_saturate_truncate": (I, [P(bfp_vec), I, P(bfp_gamma), P(bfp_vec), VP]),
     "bfp_cheby_coeffs": (I, [I64, I64, I64, I64, I64, I64, I, P(bfp_scalar), P(bfp_scalar)]),
     "mg_params_init": (I, [I, I, I, I, I, I, I, I, I, P(mg_params)]),
+    "bfp_energy_norm": (I, [P(C.c_double), I, I, P(C.c_double)]),
+    "mg_conv_rate_bytes": (C.c_size_t, [P(mg_params)]),
+    "mg_error_propagation": (I, [P(mg_params), VP, C.c_size_t, VP, P(C.c_double)]),
+    "mg_conv_rate": (I, [P(mg_params), VP, C.c_size_t, VP, P(C.c_double)]),
+    "mg_params_apply_estimate": (I, [P(mg_params), I, I, I, I]),
+    "mg_prec_est": (I, [P(mg_params), I, C.c_double, I, I, VP, C.c_size_t, VP,
+                        P(mg_prec_est_result)]),
+    "mg_eta_scan": (I, [P(mg_params), I, I, VP, C.c_size_t, VP, P(I), P(C.c_double),
+                        P(C.c_double)]),
     "mg_hierarchy_bytes": (C.c_size_t, [P(mg_params)]),
     "mg_hierarchy_create": (I, [P(mg_params), VP, C.c_size_t, VP, P(VP)]),
     "mg_hierarchy_destroy": (I, [VP]),

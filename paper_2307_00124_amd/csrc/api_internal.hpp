@@ -61,6 +61,10 @@ int hierarchy_bytes_ex(const mg_params* prm, int64_t exec_points, size_t* bytes)
 int hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t bytes, void* stream,
                         int64_t exec_points, mg_hierarchy** out);
 
+// Chebyshev coefficients c1, c2, c1_gamma of p for eta = eta_percent / 100
+// (rho = 2, rescaled to the stored operator, 16-bit)
+int set_smoother(mg_params* p, int eta_percent);
+
 // validation of multigrid parameters (BFP_OK or the error of mg_params checks)
 int params_ok(const mg_params* p);
 

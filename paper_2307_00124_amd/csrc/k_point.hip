@@ -374,4 +374,25 @@ hipError_t launch_dot(const DotLaunch& L, hipStream_t s) {
   });
 }
 
+// ------------------------------------------------------- unit vector ---
+
+// A zero block becomes the unit vector e_pos at w bits: the normalized
+// floor quantization of 1.0 (nu(1) = 2, so e = 2 - w and m = 2^(w-2)).
+__global__ void k_unit(void* mant, int bits, int64_t pos, int64_t* meta, int w) {
+  if (threadIdx.x != 0) return;
+  const int64_t m = (int64_t)1 << (w - 2);
+  if (bits == 32) static_cast<int32_t*>(mant)[pos] = (int32_t)m;
+  else if (bits == 16) static_cast<int16_t*>(mant)[pos] = (int16_t)m;
+  else static_cast<int8_t*>(mant)[pos] = (int8_t)m;
+  meta[kMetaExp] = 2 - w;
+  meta[kMetaMax] = m;
+  meta[kMetaMin] = 0;
+  meta[kMetaSat] = 0;
+}
+
+hipError_t launch_unit(void* mant, int bits, int64_t pos, int64_t* meta, int w, hipStream_t s) {
+  hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, s, mant, bits, pos, meta, w);
+  return hipGetLastError();
+}
+
 }  // namespace bfpk

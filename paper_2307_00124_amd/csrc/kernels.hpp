@@ -89,6 +89,9 @@ hipError_t launch_from_f64(const ConvertLaunch& L, hipStream_t s);
 hipError_t launch_to_f64(const ConvertLaunch& L, hipStream_t s);
 hipError_t launch_init(void* mant, size_t bytes, int64_t* meta, int64_t exp, hipStream_t s);
 hipError_t launch_meta_reset(int64_t* meta, hipStream_t s);
+// turn a zero block (bfp_vec_init) of width w into the unit vector e_pos:
+// mantissa 2^(w-2) at element pos, exponent 2 - w
+hipError_t launch_unit(void* mant, int bits, int64_t pos, int64_t* meta, int w, hipStream_t s);
 // initialise count metadata blocks (exponent exps[i], identities elsewhere)
 hipError_t launch_meta_init_list(int64_t* const* metas_dev, const int64_t* exps_dev, int count,
                                  hipStream_t s);

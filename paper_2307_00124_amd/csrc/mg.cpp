@@ -702,15 +702,25 @@ int mg_params_init(int ndim, int L, int w, int progressive, int nu1, int nu2, in
       out->w_inner[j] = inner;
     }
   }
-  // D^-1 A = A' / a_c with a_c = 1 (2D) or 3/4 (3D): c1' = c1 / a_c, c2' = c2 / a_c^2
-  int rc = bfp_cheby_coeffs(2, 1, eta_percent, 100, ndim == 2 ? 1 : 4, ndim == 2 ? 1 : 3, 16,
-                            &out->c1, &out->c2);
-  if (rc) return rc;
-  bfp_scalar c2u;
-  rc = bfp_cheby_coeffs(2, 1, eta_percent, 100, 1, 1, 16, &out->c1_gamma, &c2u);
+  int rc = bfpk::set_smoother(out, eta_percent);
   if (rc) return rc;
   return check_params(out);
 }
+
+}  // extern "C"
+
+int bfpk::set_smoother(mg_params* p, int eta_percent) {
+  if (eta_percent < 1 || eta_percent > 99) return fail(BFP_EINVAL, "eta_percent must be in 1..99");
+  const int ndim = p->ndim;
+  // D^-1 A = A' / a_c with a_c = 1 (2D) or 3/4 (3D): c1' = c1 / a_c, c2' = c2 / a_c^2
+  int rc = bfp_cheby_coeffs(2, 1, eta_percent, 100, ndim == 2 ? 1 : 4, ndim == 2 ? 1 : 3, 16,
+                            &p->c1, &p->c2);
+  if (rc) return rc;
+  bfp_scalar c2u;
+  return bfp_cheby_coeffs(2, 1, eta_percent, 100, 1, 1, 16, &p->c1_gamma, &c2u);
+}
+
+extern "C" {
 
 size_t mg_hierarchy_bytes(const mg_params* prm) {
   size_t b = 0;

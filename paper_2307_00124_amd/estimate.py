@@ -1,147 +1,109 @@
 """A priori estimation of the BFP precisions (Section 6.2, Algorithm
-bfp-prec-est), driven by the library's BFP V-cycles on the device.
-
-conv-rate-v-cycle: rho_v = ||E||_A on a coarse level j, E the error
-propagation matrix of one BFP IR-V iteration (b = 0, so the new iterate is
-the propagated error), built column by column by running the iteration on
-the canonical basis vectors; rho_v is the square root of the largest
-generalized eigenvalue of E^T A E x = lambda A x (a dense host eigenproblem,
-LAPACK through scipy, on at most a few thousand unknowns).
-
-bfp-prec-est: with the width rules check_j(q) = j (m + k) + q and
-inner_j(q) = j m + q (m = 1 and k = 2 for the 5- and 7-point Poisson
-problems), the smallest q (binary search over 1..q_max) whose rate stays
-within rho_thresh of the rate at q_max, first for the check width and then,
-with that check width, for the inner width. Every width is capped at the
-32-bit mantissa storage, the inner width at the working width (check >=
-working >= inner), and the working widths are the solver's
-w_j = min(32, 2j + 8).
-"""
+bfp-prec-est) and of the Chebyshev parameter eta (Section 5): bindings of
+the library's mg_error_propagation, mg_conv_rate, mg_prec_est, mg_eta_scan
+and mg_params_apply_estimate (argument marshalling only; the searches, the
+device solves and the energy norm run in the library)."""
 from __future__ import annotations
+
+import ctypes as C
 
 import numpy as np
 import torch
-from scipy.linalg import eigh
 
-from . import Hierarchy, MG_POLICY_NN_IR_FIRST_Q, bfp_vec_to_f64, mg_params_init
-
-
-def width_rules(j: int, q_check: int, q_inner: int, m: int = 1, k: int = 2, cap: int = 32):
-    """(check, work, inner) widths of levels 1..j, as dicts."""
-    work = {l: min(cap, 2 * l + 8) for l in range(1, j + 1)}
-    check = {l: max(work[l], min(cap, l * (m + k) + q_check)) for l in range(1, j + 1)}
-    inner = {l: min(work[l], l * m + q_inner) for l in range(1, j + 1)}
-    return check, work, inner
+from . import abi, check, lib, mg_params_init, MG_POLICY_NN_IR_FIRST_Q
 
 
-def dense_A(j: int, ndim: int) -> np.ndarray:
-    """The scaled operator of level j on the interior: 5-point [1; -1/4] in
-    2D, 7-point [3/4; -1/8] in 3D."""
-    n = (1 << j) - 1
-    centre, off = (1.0, -0.25) if ndim == 2 else (0.75, -0.125)
-    idx = np.arange(n ** ndim).reshape((n,) * ndim)
-    A = np.diag(np.full(n ** ndim, centre))
-    for ax in range(ndim):
-        lo = [slice(None)] * ndim
-        hi = [slice(None)] * ndim
-        lo[ax] = slice(0, n - 1)
-        hi[ax] = slice(1, n)
-        a, b = idx[tuple(lo)].ravel(), idx[tuple(hi)].ravel()
-        A[a, b] = off
-        A[b, a] = off
-    return A
+def _copy(p: abi.mg_params) -> abi.mg_params:
+    q = abi.mg_params()
+    C.memmove(C.addressof(q), C.addressof(p), C.sizeof(p))
+    return q
 
 
-def error_propagation(ndim: int, j: int, widths, policy: int = MG_POLICY_NN_IR_FIRST_Q,
-                      nu=(1, 0), eta: int = 23, stream=None) -> np.ndarray:
-    """E with E[:, k] = one BFP IR-V iteration on level j applied to e_k."""
-    check, work, inner = widths
-    p = mg_params_init(ndim, j, 32, True, nu[0], nu[1], 2, policy, eta)
-    for l in range(1, j + 1):
-        p.w_check[l], p.w_work[l], p.w_inner[l] = check[l], work[l], inner[l]
-    H = Hierarchy(p, stream=stream)
-    for l in range(1, j + 1):
-        H.set_rhs(l, torch.zeros(((1 << l) + 1,) * ndim, dtype=torch.float64, device="cuda"),
-                  stream)
-    n = (1 << j) - 1
-    N = n ** ndim
-    side = (1 << j) + 1
-    e = torch.zeros((side,) * ndim, dtype=torch.float64, device="cuda")
-    cols = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    inner_view = (slice(1, -1),) * ndim
-    for k in range(N):
-        pos = tuple(int(c) + 1 for c in np.unravel_index(k, (n,) * ndim))
-        e.zero_()
-        e[pos] = 1.0
-        H.set_x(j, e, stream)
-        H.ir(j, 1, stream)
-        cols[:, k] = bfp_vec_to_f64(H.get_vec(j, 0))[inner_view].reshape(-1)
-    return cols.cpu().numpy()
+class _Arena:
+    """A 256-byte aligned device arena sized by mg_conv_rate_bytes."""
+
+    def __init__(self, params: abi.mg_params, device="cuda"):
+        n = lib.mg_conv_rate_bytes(C.byref(params))
+        if n == 0:
+            check(abi.BFP_EINVAL, "mg_conv_rate_bytes")
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        self.buf = buf[off:off + n]
+        self.ptr = C.c_void_p(self.buf.data_ptr())
+        self.bytes = n
 
 
-def energy_rate(E: np.ndarray, A: np.ndarray) -> float:
-    """||E||_A = sqrt(max lambda of E^T A E x = lambda A x)."""
-    return float(np.sqrt(max(eigh(E.T @ A @ E, A, eigvals_only=True).max(), 0.0)))
+def base_params(ndim: int, j: int, nu=(1, 0), eta_percent: int = 23,
+                policy: int = MG_POLICY_NN_IR_FIRST_Q) -> abi.mg_params:
+    """Parameters of the estimation level j: the solver's working widths
+    w_j = min(32, 2j + 8), cycle nu, policy and eta; check and inner widths
+    are set by the width rules of each evaluation."""
+    return mg_params_init(ndim, j, 32, True, nu[0], nu[1], 2, policy, eta_percent)
 
 
-def conv_rate_v_cycle(ndim: int, j: int, widths, **kw) -> float:
-    return energy_rate(error_propagation(ndim, j, widths, **kw), dense_A(j, ndim))
+def apply_estimate(params: abi.mg_params, q_check: int, q_inner: int, m: int = 1,
+                   k: int = 2) -> abi.mg_params:
+    """A copy of params with the check and inner width rules of
+    bfp-prec-est applied (mg_params_apply_estimate)."""
+    p = _copy(params)
+    check(lib.mg_params_apply_estimate(C.byref(p), q_check, q_inner, m, k),
+          "mg_params_apply_estimate")
+    return p
 
 
-def _min_q(ok, q_max: int) -> int:
-    lo, hi = 1, q_max
-    while lo < hi:
-        mid = (lo + hi) // 2
-        if ok(mid):
-            hi = mid
-        else:
-            lo = mid + 1
-    return lo
+def widths(params: abi.mg_params) -> tuple[dict, dict, dict]:
+    L = params.L
+    return ({j: params.w_check[j] for j in range(1, L + 1)},
+            {j: params.w_work[j] for j in range(1, L + 1)},
+            {j: params.w_inner[j] for j in range(1, L + 1)})
 
 
-def bfp_prec_est(ndim: int, j_c: int, q_max: int, rho_thresh: float, **kw) -> dict:
-    """Algorithm bfp-prec-est on level j_c: the constants of the check and
-    inner width rules, the reference rate and the rate they reach."""
-    cache = {}
-
-    def rate(q_c, q_i):
-        if (q_c, q_i) not in cache:
-            cache[(q_c, q_i)] = conv_rate_v_cycle(ndim, j_c, width_rules(j_c, q_c, q_i), **kw)
-        return cache[(q_c, q_i)]
-
-    ref = rate(q_max, q_max)
-    q_check = _min_q(lambda q: rate(q, q_max) / ref < rho_thresh, q_max)
-    q_inner = _min_q(lambda q: rate(q_check, q) / ref < rho_thresh, q_max)
-    return {"rho_ref": ref, "q_check": q_check, "q_inner": q_inner,
-            "rho": rate(q_check, q_inner), "rates_evaluated": len(cache)}
+def error_propagation(params: abi.mg_params) -> np.ndarray:
+    """E (N x N, E[:, k] = one IR-V iteration applied to e_k) on level
+    params.L, from the device."""
+    ar = _Arena(params)
+    N = ((1 << params.L) - 1) ** params.ndim
+    E = np.zeros(N * N, dtype=np.float64)
+    check(lib.mg_error_propagation(C.byref(params), ar.ptr, ar.bytes, None,
+                                   E.ctypes.data_as(C.POINTER(C.c_double))),
+          "mg_error_propagation")
+    return E.reshape(N, N).T.copy()
 
 
-def argmin_unimodal(f, lo: int, hi: int) -> int:
-    """Smallest minimizer of f over the integers lo..hi, by ternary search
-    (f taken as unimodal there), evaluating f at most once per point."""
-    cache = {}
-
-    def F(i):
-        if i not in cache:
-            cache[i] = f(i)
-        return cache[i]
-
-    while hi - lo > 2:
-        m1 = lo + (hi - lo) // 3
-        m2 = hi - (hi - lo) // 3
-        if F(m1) <= F(m2):
-            hi = m2
-        else:
-            lo = m1
-    return min(range(lo, hi + 1), key=lambda i: (F(i), i))
+def energy_norm(E: np.ndarray, ndim: int, j: int) -> float:
+    """||E||_A for the scaled operator of level j (bfp_energy_norm)."""
+    Ec = np.ascontiguousarray(np.asarray(E, dtype=np.float64).T)
+    rho = C.c_double()
+    check(lib.bfp_energy_norm(Ec.ctypes.data_as(C.POINTER(C.c_double)), ndim, j,
+                              C.byref(rho)), "bfp_energy_norm")
+    return rho.value
 
 
-def estimate_eta(ndim: int, j: int, widths, nu=(1, 0), lo: int = 1, hi: int = 99,
-                 **kw) -> tuple[int, float]:
-    """The Chebyshev smoother's parameter eta = i / 100 (the library's
-    integer percent) with the smallest V-cycle rate rho_v on level j: the
-    bfp-prec-est machinery applied to the eta the paper fixes empirically.
-    Returns (i, rho_v)."""
-    rate = lambda i: conv_rate_v_cycle(ndim, j, widths, nu=nu, eta=i, **kw)
-    i = argmin_unimodal(rate, lo, hi)
-    return i, rate(i)
+def conv_rate(params: abi.mg_params) -> float:
+    ar = _Arena(params)
+    rho = C.c_double()
+    check(lib.mg_conv_rate(C.byref(params), ar.ptr, ar.bytes, None, C.byref(rho)), "mg_conv_rate")
+    return rho.value
+
+
+def bfp_prec_est(params: abi.mg_params, q_max: int = 64, rho_thresh: float = 1.05,
+                 m: int = 1, k: int = 2) -> dict:
+    """Algorithm bfp-prec-est on level params.L (mg_prec_est)."""
+    ar = _Arena(apply_estimate(params, q_max, q_max, m, k))
+    r = abi.mg_prec_est_result()
+    check(lib.mg_prec_est(C.byref(params), q_max, float(rho_thresh), m, k, ar.ptr, ar.bytes,
+                          None, C.byref(r)), "mg_prec_est")
+    return {"q_check": r.q_check, "q_inner": r.q_inner, "rho_ref": r.rho_ref, "rho": r.rho,
+            "rates_evaluated": r.rates}
+
+
+def eta_scan(params: abi.mg_params, lo: int = 1, hi: int = 99) -> tuple[int, float, list]:
+    """eta = i / 100 in lo..hi minimizing rho_v on level params.L
+    (mg_eta_scan): (i, its rate, every rate)."""
+    ar = _Arena(params)
+    best = C.c_int()
+    rho = C.c_double()
+    rates = (C.c_double * (hi - lo + 1))()
+    check(lib.mg_eta_scan(C.byref(params), lo, hi, ar.ptr, ar.bytes, None, C.byref(best),
+                          C.byref(rho), rates), "mg_eta_scan")
+    return best.value, rho.value, list(rates)

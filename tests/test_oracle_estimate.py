@@ -69,17 +69,17 @@ def test_estimation_meets_the_criterion_minimally():
     assert r["q_check"] == 1
 
 
-def test_argmin_unimodal():
-    f = lambda i: (i - 37) ** 2
-    assert est.argmin_unimodal(f, 1, 99) == 37
-    assert est.argmin_unimodal(lambda i: abs(i - 5) // 2, 1, 20) == 4   # ties: the smallest
-
-
-def test_eta_search_finds_the_exhaustive_minimum():
-    """On level 3 the rate is unimodal in eta over 15..35 %: the ternary
-    search returns the exhaustive argmin."""
-    wd = est.width_rules(3, 16, 16)
+def test_eta_scan_against_the_fp64_vcycle():
+    """The scan over eta = i / 100 (every i, Section 5) on level 3 with the
+    widths at the cap: each BFP rate lies within 3 % of the FP64 V-cycle's
+    rate with exact coefficients (the 14-bit working width of level 3 and
+    the 16-bit coefficients perturb it), and the chosen i is the FP64
+    V-cycle's minimizer. The BFP rates are not unimodal in eta here (24 %
+    beats 25 %, 26 % beats both), so only a full scan finds the minimum."""
+    from oracle import cheby
+    wd = est.width_rules(3, 40, 40)
     i, rho = est.estimate_eta(2, 3, wd, lo=15, hi=35)
-    rates = {k: est.conv_rate_v_cycle(2, 3, wd, eta=Fraction(k, 100)) for k in range(15, 36)}
-    best = min(rates, key=lambda k: (rates[k], k))
-    assert i == best and rho == pytest.approx(rates[best])
+    f64 = {k: cheby.vcycle_rate(2, 3, *map(float, mg.cheby_nodes(2, Fraction(k, 100))))
+           for k in range(15, 36)}
+    assert i == min(f64, key=lambda k: (f64[k], k))
+    assert rho == pytest.approx(f64[i], rel=0.03)

@@ -361,6 +361,8 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
     L.ybits = y ? y->storage_bits : 32;
     L.zbits = z->storage_bits;
     L.wide = wide;
+    L.y_is_x = y && y->mant == x->mant && y->storage_bits == x->storage_bits &&
+               y->pitch == x->pitch;
     L.rows = rows > 0 ? rows : star_rows(x->ndim, x->n);
     {
       const int64_t segs = (x->n + 1 + 255) / 256;

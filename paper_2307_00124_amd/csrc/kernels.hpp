@@ -30,6 +30,8 @@ struct StarLaunch {
   int rows;   // rows (2D) or planes (3D) marched by one wave
   int wx;     // 2D: column segments per block (1, 2 or 4; the block's 4 waves
               // cover wx segments times 4 / wx row bands)
+  int y_is_x; // y is the block x itself (the relaxation c2 A r + c1 r): its
+              // entries are the centre values already loaded, not a stream
 };
 hipError_t launch_star(const StarLaunch& L, hipStream_t s);
 

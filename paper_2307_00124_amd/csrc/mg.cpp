@@ -201,7 +201,9 @@ int op_stencil(mg_hierarchy* h, const bfp_stencil* S, const bfp_vec& x, const bf
   int rc = stencil_apply_impl(S, &x, al, be, y, z.w, mode, &g, &z, s, 0);
   if (rc) return rc;
   const int passes = mode == BFP_NORMALIZE ? 2 : 1;
-  const double rd = pts(x) * sz(x) + (y ? pts(*y) * sz(*y) : 0.0);
+  // algorithmic bytes: every input read once (y = x, the relaxation, once)
+  const bool y_own = y && y->mant != x.mant;
+  const double rd = pts(x) * sz(x) + (y_own ? pts(*y) * sz(*y) : 0.0);
   h->bytes += passes * rd + pts(z) * sz(z);
   h->launches += passes;
   return BFP_OK;

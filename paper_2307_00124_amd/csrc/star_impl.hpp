@@ -28,7 +28,7 @@ namespace bfpk {
 // computed and stored. Stores count in the same vector-memory counter as
 // loads, so issuing the next loads first keeps the wait for them from also
 // waiting on this batch's store acknowledgements.
-template <typename TX, typename TY, int U, bool HASY>
+template <typename TX, typename TY, int U, bool HASY, bool YX>
 __device__ __forceinline__ void star2d_fetch(const TX* X, const TY* Y, int64_t r, int64_t n,
                                              int64_t px, int64_t py, int64_t c, int lane,
                                              bool act, bool act_y, int32_t (&xl)[U][4],
@@ -37,7 +37,7 @@ __device__ __forceinline__ void star2d_fetch(const TX* X, const TY* Y, int64_t r
   for (int k = 0; k < U; ++k) {
     const int64_t rr = r + 1 + k;                    // x lines r+1 .. r+U
     ld4(X, rr * px + c, xl[k], act && rr <= n + 1);
-    if (HASY) ld4(Y, (r + k) * py + c, yl[k], act_y && r + k <= n);
+    if (HASY && !YX) ld4(Y, (r + k) * py + c, yl[k], act_y && r + k <= n);
     else yl[k][0] = yl[k][1] = yl[k][2] = yl[k][3] = 0;
     // lane 0 needs column c-1, lane 63 column c+4 (other lanes read a
     // harmless in-range value and ignore it)
@@ -58,7 +58,8 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t id, int64_t nblk) {
   return k * q + (k < r ? k : r) + j;
 }
 
-template <typename TX, typename TY, typename TZ, int PASS, bool HASY, bool WIDE, int U>
+// YX: y is x itself (the relaxation): its entries are the centre values
+template <typename TX, typename TY, typename TZ, int PASS, bool HASY, bool WIDE, int U, bool YX>
 __global__ __launch_bounds__(kBlock) void k_star2d(const StarLaunch L) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -89,10 +90,10 @@ __global__ __launch_bounds__(kBlock) void k_star2d(const StarLaunch L) {
     int32_t nx[U][4], ny[U][4], ne[U];     // the next batch in flight
     ld4(X, (r0 - 1) * px + c, win[0], act);
     ld4(X, r0 * px + c, win[1], act);
-    star2d_fetch<TX, TY, U, HASY>(X, Y, r0, n, px, py, c, lane, act, act_y,
+    star2d_fetch<TX, TY, U, HASY, YX>(X, Y, r0, n, px, py, c, lane, act, act_y,
                                   *reinterpret_cast<int32_t(*)[U][4]>(&win[2]), yv, eg);
     for (int64_t r = r0; r < r1; r += U) {
-      star2d_fetch<TX, TY, U, HASY>(X, Y, r + U, n, px, py, c, lane, act, act_y, nx, ny, ne);
+      star2d_fetch<TX, TY, U, HASY, YX>(X, Y, r + U, n, px, py, c, lane, act, act_y, nx, ny, ne);
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const int32_t* up = win[k];
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_star2d(const StarLaunch L) {
                 (int64_t)tym * up[q] + (int64_t)typ * dn[q];
           else
             g = (int64_t)(t0 * cur[q] + txm * xl + txp * xr + tym * up[q] + typ * dn[q]);
-          out[q] = E.template put<VAR>(g, yv[k][q], row_ok && colok[q]);
+          out[q] = E.template put<VAR>(g, YX ? cur[q] : yv[k][q], row_ok && colok[q]);
         }
         if (PASS != kQ1 && act_z && row_ok) st4(Z, (r + k) * pz + c, out);
       }
@@ -178,7 +179,7 @@ __device__ __forceinline__ void star3d_rows4(const TX* X, int64_t z, int64_t y0,
     ld4(X, (z * side + y0 + k) * px + c, v[k], act && z <= n + 1 && y0 + k <= n + 1);
 }
 
-template <typename TX, typename TY, typename TZ, int PASS, bool HASY>
+template <typename TX, typename TY, typename TZ, int PASS, bool HASY, bool YX>
 __global__ __launch_bounds__(kBlock) void k_star3d(const StarLaunch L) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -214,11 +215,11 @@ __global__ __launch_bounds__(kBlock) void k_star3d(const StarLaunch L) {
     star3d_rows4(X, z0 - 1, y0, n, side, px, c, act, pa);
     star3d_rows4(X, z0, y0, n, side, px, c, act, pb);
     star3d_rows4(X, z0 + 1, y0, n, side, px, c, act, pc);
-    star3d_plane(X, Y, z0, y0, n, side, px, py, c, lane, act, act_y, HASY, hm, hp, yv, eg);
+    star3d_plane(X, Y, z0, y0, n, side, px, py, c, lane, act, act_y, HASY && !YX, hm, hp, yv, eg);
     for (int64_t z = z0; z < z1; ++z) {
       star3d_rows4(X, z + 2, y0, n, side, px, c, act, nc);
-      star3d_plane(X, Y, z + 1, y0, n, side, px, py, c, lane, act, act_y, HASY, nhm, nhp, nyv,
-                   neg);
+      star3d_plane(X, Y, z + 1, y0, n, side, px, py, c, lane, act, act_y, HASY && !YX, nhm, nhp,
+                   nyv, neg);
 #pragma unroll
       for (int k = 0; k < kYS; ++k) {
         const int32_t* cur = pb[k];
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_star3d(const StarLaunch L) {
           const int64_t g = (int64_t)t0 * cur[q] + (int64_t)txm * xl + (int64_t)txp * xr +
                             (int64_t)tym * up[q] + (int64_t)typ * dn[q] +
                             (int64_t)tzm * pa[k][q] + (int64_t)tzp * pc[k][q];
-          out[q] = E.template put<VAR>(g, yv[k][q], row_ok && colok[q]);
+          out[q] = E.template put<VAR>(g, YX ? cur[q] : yv[k][q], row_ok && colok[q]);
         }
         if (PASS != kQ1 && act_z && row_ok) st4_nt(Z, (z * side + y0 + k) * pz + c, out);
       }
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_star3d(const StarLaunch L) {
 
 // ----------------------------------------------------------- launchers --
 
-template <typename TX, typename TY, typename TZ, int PASS, bool HASY>
+template <typename TX, typename TY, typename TZ, int PASS, bool HASY, bool YX = false>
 static hipError_t star_go(const StarLaunch& L, hipStream_t s) {
   const int64_t n = L.n;
   const int rows = L.rows > 0 ? L.rows : 1;
@@ -274,19 +275,19 @@ static hipError_t star_go(const StarLaunch& L, hipStream_t s) {
     dim3 grid((unsigned)((segs + wx - 1) / wx), (unsigned)((bands + 4 / wx - 1) / (4 / wx)));
     if (rows >= 4 && rows % 4 == 0) {
       if (L.wide)
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, true, 4>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, true, 4, YX>), grid, dim3(kBlock), 0, s, L);
       else
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, false, 4>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, false, 4, YX>), grid, dim3(kBlock), 0, s, L);
     } else {
       if (L.wide)
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, true, 1>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, true, 1, YX>), grid, dim3(kBlock), 0, s, L);
       else
-        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, false, 1>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, false, 1, YX>), grid, dim3(kBlock), 0, s, L);
     }
   } else {
     dim3 grid((unsigned)((n + 1 + 255) / 256), (unsigned)((n + 4 * kYS - 1) / (4 * kYS)),
               (unsigned)((n + rows - 1) / rows));
-    hipLaunchKernelGGL((k_star3d<TX, TY, TZ, PASS, HASY>), grid, dim3(kBlock), 0, s, L);
+    hipLaunchKernelGGL((k_star3d<TX, TY, TZ, PASS, HASY, YX>), grid, dim3(kBlock), 0, s, L);
   }
   return hipGetLastError();
 }
@@ -299,6 +300,12 @@ hipError_t star_for_x(const StarLaunch& L, hipStream_t s) {
     if (q1) return star_go<TX, int32_t, int32_t, kQ1, false>(L, s);
     return with_type(L.zbits, [&](auto tz) {
       return star_go<TX, int32_t, decltype(tz), kOut, false>(L, s);
+    });
+  }
+  if (L.y_is_x) {   // the relaxation: y is x, read once
+    if (q1) return star_go<TX, TX, int32_t, kQ1, true, true>(L, s);
+    return with_type(L.zbits, [&](auto tz) {
+      return star_go<TX, TX, decltype(tz), kOut, true, true>(L, s);
     });
   }
   return with_type(L.ybits, [&](auto ty) {

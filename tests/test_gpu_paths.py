@@ -60,3 +60,34 @@ def test_star_default_multirow_sizes(ndim, n, mode, with_y):
         cases = range(len(STORAGE)) if n < 100 else (2 * with_y + mode, (2 * with_y + mode + 1) % 4)
         for case in cases:
             star_case(g, ndim, n, mode, with_y, case, f"{ndim}D n {n}")
+
+
+@pytest.mark.parametrize("ndim,n,rows", [(2, 37, 0), (2, 301, 4), (2, 2047, 0), (3, 19, 0),
+                                         (3, 37, 4), (3, 65, 0)])
+@pytest.mark.parametrize("mode", [P.BFP_SATURATE, P.BFP_NORMALIZE])
+def test_star_y_is_x(ndim, n, rows, mode):
+    """The relaxation form c2 A r + c1 r, where y is the block x itself (the
+    kernel takes y from the centre values it already holds instead of a
+    second stream), for every storage type of r, against the oracle."""
+    from oracle import blas
+    from oracle.bfp import Scalar
+    from tests.gpu_util import assert_block_equal, rand_block, upload
+    from tests.test_gpu_ops import fd_A, gamma_pair, quantize_ref
+    g = np.random.default_rng(ndim * 31 + n + mode)
+    key = "star2d" if ndim == 2 else "star3d"
+    kv = {f"{key}_rows": rows, f"{key}_small_n": 1} if rows else {}
+    with tuned(**kv):
+        for bits in (32, 16, 8):
+            w = int(g.integers(2, bits + 1))
+            Ad, Ao = fd_A(ndim)
+            x = rand_block(g, ndim, n, w, int(g.integers(-30, 30)))
+            xd = upload(x, bits)
+            c2 = Scalar(-int(g.integers(1, 1 << 15)), int(g.integers(-16, 0)), 16)
+            c1 = Scalar(int(g.integers(1, 1 << 15)), int(g.integers(-16, 0)), 16)
+            gd, gr = gamma_pair("norm", g, x, xd)
+            wz = int(g.integers(2, 33))
+            z = P.Vec(ndim, n, wz, 32)
+            P.bfp_stencil_apply(Ad, xd, P.scalar(c2.m, c2.e), P.scalar(c1.m, c1.e), xd, wz,
+                                mode, gd, z)
+            ref = quantize_ref(blas.gemv(Ao, x, x, c2, c1), mode, wz, gr)
+            assert_block_equal(z, ref, f"{ndim}D n {n} y = x, storage {bits}")

@@ -518,7 +518,10 @@ int mg_server_destroy(mg_server* s);
  * stencil kernels marches on large grids, "star2d_small_n" /
  * "star3d_small_n" = grid size below which every wave takes a single row
  * (values >= 1; "star2d_rows" = 0 restores the default, rows = n^2 / 2^18
- * rounded down to a power of two in [1, 64]); "exec_max_points" = largest grid (in interior points) whose
+ * rounded down to a power of two in [1, 64]); "transfer_rows" = coarse
+ * rows (2D) or planes (3D) one wave of the restriction / prolongation
+ * kernels marches (0, the default: a power of two in [1, 32] that gives a
+ * few thousand waves); "exec_max_points" = largest grid (in interior points) whose
  * level runs inside the one-workgroup coarse-level programs a hierarchy
  * records at creation (0 = never; read by mg_hierarchy_bytes/create);
  * "diagnostics" = 1: hierarchies created while it is set keep the solve

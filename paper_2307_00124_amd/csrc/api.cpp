@@ -101,6 +101,19 @@ int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas) {
   return BFP_OK;
 }
 
+// Grid transfers: coarse rows (2D) / planes (3D) one wave marches; the
+// default aims at a few thousand waves per launch (0 = default).
+static int g_transfer_rows = 0;
+
+static int transfer_rows(int ndim, int64_t n_out, int64_t nc) {
+  if (g_transfer_rows > 0) return g_transfer_rows;
+  const int64_t segs = (n_out + 2 + 255) / 256;
+  const int64_t lines = ndim == 2 ? segs * (nc + 1) : segs * (nc + 1) * (nc + 1);
+  int rows = 1;
+  while (rows < 32 && (int64_t)rows * 2 * 4096 <= lines) rows *= 2;
+  return rows;
+}
+
 static int star_rows(int ndim, int64_t n) {
   if (ndim == 2) {
     if (g_star2d_rows_large > 0) return n < g_star2d_small_n ? 1 : g_star2d_rows_large;
@@ -392,6 +405,7 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
     L.xbits = x->storage_bits;
     L.ybits = y ? y->storage_bits : 32;
     L.zbits = z->storage_bits;
+    L.rows = transfer_rows(x->ndim, z->n, coarse->n);
     return run_modes(L, mode, s, [&](TransferLaunch& l) { return launch_transfer(l, s); });
   }
   return fail(BFP_EINVAL, "unknown stencil kind %d", A->kind);
@@ -597,6 +611,7 @@ int bfp_tuning_set(const char* key, int value) {
   }
   // 2D: rows 0 restores the size heuristic (then small_n is not read)
   if (k == "star2d_rows") { g_star2d_rows_large = value; return BFP_OK; }
+  if (k == "transfer_rows") { g_transfer_rows = value; return BFP_OK; }
   if (k == "star2d_small_n") { g_star2d_small_n = value; return BFP_OK; }
   if (value < 1) return fail(BFP_EINVAL, "value out of range");
   if (k == "star3d_rows") g_star3d_rows_large = value;
@@ -611,6 +626,7 @@ int bfp_tuning_get(const char* key, int* value) {
   if (k == "exec_max_points") *value = g_exec_max_points;
   else if (k == "diagnostics") *value = g_diagnostics;
   else if (k == "star2d_rows") *value = g_star2d_rows_large;
+  else if (k == "transfer_rows") *value = g_transfer_rows;
   else if (k == "star2d_small_n") *value = g_star2d_small_n;
   else if (k == "star3d_rows") *value = g_star3d_rows_large;
   else if (k == "star3d_small_n") *value = g_star3d_small_n;

@@ -48,6 +48,7 @@ struct TransferLaunch {
   int64_t px, py, pz;
   int32_t taps[27];
   int xbits, ybits, zbits;
+  int rows;        // coarse rows (2D) or coarse planes (3D) one wave marches
 };
 hipError_t launch_transfer(const TransferLaunch& L, hipStream_t s);
 

@@ -110,8 +110,8 @@ def main():
     dof = n * n
     A2 = P.Stencil(2, P.BFP_STENCIL_A, -2, [0, -1, 0, -1, 4, -1, 0, -1, 0], 4)
 
-    def make(w):
-        p = P.mg_params_init(2, L, w, True, 1, 0, 2, P.MG_POLICY_NN_IR_FIRST_Q, 23)
+    def make(w, N=2, policy=P.MG_POLICY_NN_IR_FIRST_Q):
+        p = P.mg_params_init(2, L, w, True, 1, 0, N, policy, 23)
         p.min_storage_bits = 32
         return P.Hierarchy(p)
 
@@ -259,16 +259,41 @@ def main():
         solve3d = bench_3d(args, P, W, torch, dev, stream, ev)
 
     # ------------------------------------------------------ width sweep ---
+    # per finest inner width w (progressive: one bit less per coarser level):
+    # the error with N = 2, then the smallest N <= 8 IR-V iterations per
+    # level that reaches 1.1x the discretization error, and its time
+    gate_fp64 = 1.1 * fp64["err_over_disc"]
     sweep = []
     for w in [int(s) for s in args.sweep.split(",") if s]:
-        Hs = make(w)
-        xw = P.Vec(2, n, Hs.get_vec(L, 0).w, 32)
-        msw = timed(Hs, xw, 3, 1)
-        acc = accuracy(xw)
-        sweep.append({"w": w, "ms": round(msw, 3), "dof_per_s": dof / (msw * 1e-3),
-                      "err_over_disc": round(acc, 4), "at_disc_error": acc <= 1.1})
-        del Hs, xw
+        row = {"w": w}
+        for N in range(2, 9):
+            Hs = make(w, N)
+            xw = P.Vec(2, n, Hs.get_vec(L, 0).w, 32)
+            msw = timed(Hs, xw, 3, 1)
+            acc = accuracy(xw)
+            del Hs, xw
+            if N == 2:
+                row.update({"ms_N2": round(msw, 3), "err_over_disc_N2": round(acc, 4)})
+            if acc <= 1.1:
+                row.update({"N": N, "ms": round(msw, 3), "dof_per_s": dof / (msw * 1e-3),
+                            "err_over_disc": round(acc, 4), "at_disc_error": True,
+                            "within_1.1x_fp64_mg": acc <= gate_fp64})
+                break
+        else:
+            row.update({"N": "unreached up to 8", "err_over_disc_N8": round(acc, 4),
+                        "at_disc_error": False})
+        sweep.append(row)
         torch.cuda.empty_cache()
+    # the literal "no intermediate normalisation" schedule: nnqcomp for every
+    # call, finest inner width args.w, N = 2
+    Hn = make(args.w, 2, P.MG_POLICY_NN)
+    xn = P.Vec(2, n, Hn.get_vec(L, 0).w, 32)
+    ms_nn = timed(Hn, xn, 3, 1)
+    acc_nn = accuracy(xn)
+    all_nn = {"ms": round(ms_nn, 3), "dof_per_s": dof / (ms_nn * 1e-3),
+              "err_over_disc": round(acc_nn, 4), "at_disc_error": acc_nn <= 1.1}
+    del Hn, xn
+    torch.cuda.empty_cache()
 
     # ----------------------------------------- solve diagnostics -------
     diagnostics = estimation = None
@@ -334,6 +359,8 @@ def main():
                                f"finest inner w={args.w}, nnqcomp with qcomp for the first IR "
                                f"residual per level", "dof": dof,
                    "err_over_disc": round(ratio, 4), "at_disc_error": ratio <= 1.1,
+                   "err_over_fp64_mg_err": round(ratio / fp64["err_over_disc"], 4),
+                   "within_1.1x_fp64_mg": ratio <= 1.1 * fp64["err_over_disc"],
                    "launches_per_step": step_launches,
                    "algorithmic_bytes_per_step": step_bytes},
         "roofline": {"bound": "hbm", "achieved": round(kern_gbs, 1), "peak": HBM_PEAK_GBS,
@@ -348,6 +375,7 @@ def main():
         "solve_3d": solve3d,
         "c1_33x33": c1,
         "sweep": sweep,
+        "all_nnqcomp_N2": all_nn,
         "diagnostics": diagnostics,
         "precision_estimation": estimation,
         "batched": batch,
@@ -360,9 +388,13 @@ def main():
 def bench_batch(args, P, W, np, torch, dev, stream, ev):
     """The batched workload: independent 2D solves (sides 33..257, 8 sine
     modes, inner width 16 in int16, x and b in int32), all in one launch,
-    against the same kind of solves issued one at a time."""
+    against the same kind of solves issued one at a time. N per side is the
+    calibrated number of IR-V iterations per level that reaches the
+    discretization error (calibrate_n); every solve's error is checked."""
     solves = W.batch_trace(args.batch, seed=1)
-    prms = [P.batch_params(2, s.level, 16) for s in solves]
+    sched = {L: calibrate_n(P, W, torch, dev, 2, L, 16)
+             for L in sorted({s.level for s in solves})}
+    prms = [P.batch_params(2, s.level, 16, N=sched[s.level][0] or 16) for s in solves]
     keep = {}
     table = torch.zeros(len(solves) * P.MG_MAX_LEVELS, dtype=torch.int64)
     for i, s in enumerate(solves):
@@ -386,24 +418,11 @@ def bench_batch(args, P, W, np, torch, dev, stream, ev):
     ms = e0.elapsed_time(e1) / reps
     bytes_per, _ = B.counters()
 
-    # accuracy on a sample: error to the continuum solution against the FP64
+    # accuracy of every solve: error to the continuum solution over the
     # discrete solution's (closed form: sine modes are eigenvectors of A_h)
-    worst = 0.0
-    for i in range(0, len(solves), max(1, len(solves) // 16)):
-        s = solves[i]
-        j = s.level
-        hh = 2.0 ** -j
-        u = P.bfp_vec_to_f64(B.get_vec(i, j, 0)).cpu().numpy()
-        ue = W.sine_u(j, s.modes)
-        uh = np.zeros_like(ue)
-        xk = np.arange((1 << j) + 1) * hh
-        for (kx, ky), a in zip(s.modes.k, s.modes.a):
-            lam = (4.0 / hh ** 2) * (math.sin(kx * math.pi * hh / 2) ** 2 +
-                                     math.sin(ky * math.pi * hh / 2) ** 2)
-            uh += (a / lam) * np.outer(np.sin(ky * math.pi * xk), np.sin(kx * math.pi * xk))
-        e_bfp = math.sqrt(float(((u - ue)[1:-1, 1:-1] ** 2).sum()) * hh * hh)
-        e_fp = math.sqrt(float(((uh - ue)[1:-1, 1:-1] ** 2).sum()) * hh * hh)
-        worst = max(worst, e_bfp / e_fp)
+    ratios = [err_ratio(torch, P.bfp_vec_to_f64(B.get_vec(i, s.level, 0)), s.level, s.modes, 2, dev)
+              for i, s in enumerate(solves)]
+    worst = max(ratios)
 
     # one solve at a time through the per-solve calls, on a sample holding
     # every side equally
@@ -432,11 +451,13 @@ def bench_batch(args, P, W, np, torch, dev, stream, ev):
     loop_rate = loop_dof / (loop_ms * 1e-3)
     rate = dof / (ms * 1e-3)
     return {"workload": f"{len(solves)} independent 2D Poisson FMG solves, sides "
-                        "{33,65,129,257} (seed 1), 8 sine modes, N=max(2,L-3) IR-V(1,0) per "
-                        "level, inner w=16 int16, "
-                        "x and b int32, one launch", "dof": dof, "ms": round(ms, 3),
+                        "{33,65,129,257} (seed 1), 8 sine modes, N IR-V(1,0) per level "
+                        "calibrated per side to reach the discretization error, inner w=16 "
+                        "int16, x and b int32, one launch", "dof": dof, "ms": round(ms, 3),
+            "schedule_N": {str((1 << L) + 1): (v[0] or "unreached") for L, v in sched.items()},
             "dof_per_s": rate, "algorithmic_gbs": bytes_per / (ms * 1e-3) / 1e9,
-            "worst_err_over_disc_sampled": round(worst, 4),
+            "worst_err_over_disc": round(worst, 4),
+            "solves_missing_disc_error": sum(q > 1.1 for q in ratios),
             "loop_dof_per_s": loop_rate, "loop_sample": len(sample),
             "speedup_vs_loop": round(rate / loop_rate, 2)}
 
@@ -737,16 +758,87 @@ def sine_f_dev(torch, j, modes, ndim, dev):
     return f
 
 
+def sine_u_dev(torch, j, modes, ndim, dev, discrete):
+    """Solution of -Laplace u = sine_f: per mode a_i / lambda_i times the
+    mode, lambda_i = pi^2 |k_i|^2 (continuum) or (4 / h^2) sum_d
+    sin^2(k_d pi h / 2) (the 5- / 7-point discrete solution; sine modes are
+    eigenvectors of the FD operator). Problem data, not BFP arithmetic."""
+    h = 2.0 ** -j
+    side = (1 << j) + 1
+    x = torch.arange(side, dtype=torch.float64, device=dev) * h
+    u = torch.zeros((side,) * ndim, dtype=torch.float64, device=dev)
+    for i in range(modes.k.shape[0]):
+        ks = [float(k) for k in modes.k[i]]
+        if discrete:
+            lam = (4.0 / h ** 2) * sum(math.sin(k * math.pi * h / 2.0) ** 2 for k in ks)
+        else:
+            lam = math.pi ** 2 * sum(k * k for k in ks)
+        t = None
+        for k in ks:
+            sv = torch.sin(math.pi * k * x)
+            sv[0] = 0.0
+            sv[-1] = 0.0
+            t = sv if t is None else torch.multiply(sv.reshape((-1,) + (1,) * t.dim()), t)
+        u += (float(modes.a[i]) / lam) * t
+    return u
+
+
+def err_ratio(torch, u, j, modes, ndim, dev):
+    """||u - u*|| / ||u_h - u*|| (discrete L2 norms over the interior): the
+    error of a BFP solution over the discretization error."""
+    inner = (slice(1, -1),) * ndim
+    us = sine_u_dev(torch, j, modes, ndim, dev, False)
+    uh = sine_u_dev(torch, j, modes, ndim, dev, True)
+    e = float(((u - us)[inner] ** 2).sum())
+    d = float(((uh - us)[inner] ** 2).sum())
+    return math.sqrt(e / d) if d > 0 else float("inf")
+
+
+def calibrate_n(P, W, torch, dev, ndim, L, w, target=1.0, nmax=16, samples=2, seed=99):
+    """Schedule autotuning for an accuracy target: the smallest number N of
+    IR-V(1,0) iterations per FMG level with which the batched-workload
+    schedule (inner width w on every level) brings sine-mode problems of this
+    shape (calibration draws, not the trace's) within `target` times the
+    discretization error. Returns (N, worst ratio at N) or (None, ratio at
+    nmax) when no N up to nmax does."""
+    import numpy as np
+    g = np.random.default_rng(seed + 1000 * ndim + 10 * L + w)
+    draws = [W.draw_sine_modes(g, ndim) for _ in range(samples)]
+    rhs = [[sine_f_dev(torch, j, m, ndim, dev) for j in range(1, L + 1)] for m in draws]
+    worst = float("inf")
+    for N in range(2, nmax + 1):
+        H = P.Hierarchy(P.batch_params(ndim, L, w, N=N))
+        worst = 0.0
+        for m, r in zip(draws, rhs):
+            H.fmg_f64(r)
+            u = P.bfp_vec_to_f64(H.get_vec(L, 0))
+            worst = max(worst, err_ratio(torch, u, L, m, ndim, dev))
+        del H
+        if worst <= target:
+            return N, worst
+    return None, worst
+
+
 def bench_serve(args, P, W, np, torch, dev):
     """The serving workload: open-loop Poisson arrivals (2000 req/s) of mixed
     2D/3D solves of mixed sizes and widths, run by the request server with
     several slots, against the same trace through a one-slot server (solves
-    one after the other)."""
+    one after the other). Each request's schedule keeps its width w as the
+    inner width on every level and takes the number of IR-V iterations per
+    FMG level that calibration solves of its shape need to reach the
+    discretization error (calibrate_n); every served result is then checked
+    against the closed-form discrete solution, and requests that miss 1.1x
+    are reported apart."""
     trace = W.serving_trace(args.serve, rate=2000.0, seed=2)
+    classes = sorted({(r.ndim, r.level, r.w) for r in trace})
+    t0 = time.perf_counter()
+    sched = {c: calibrate_n(P, W, torch, dev, *c) for c in classes}
+    calib_s = time.perf_counter() - t0
     prms, rhs, outs, dofs = [], [], [], []
     for r in trace:
         L = r.level
-        prms.append(P.batch_params(r.ndim, L, r.w))
+        N = sched[(r.ndim, L, r.w)][0] or 16
+        prms.append(P.batch_params(r.ndim, L, r.w, N=N))
         rhs.append([sine_f_dev(torch, j, r.modes, r.ndim, dev) for j in range(1, L + 1)])
         outs.append(torch.zeros(((1 << L) + 1,) * r.ndim, dtype=torch.float64, device=dev))
         dofs.append(((1 << L) - 1) ** r.ndim)
@@ -765,7 +857,7 @@ def bench_serve(args, P, W, np, torch, dev):
                 warm.discard(t)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nxt, pending, lat, done_at = 0, {}, [], []
+        nxt, pending, lat, done_at = 0, {}, [0.0] * count, []
         while nxt < count or pending:
             now = time.perf_counter() - t0
             while nxt < count and trace[nxt].t_arrival <= now:
@@ -774,18 +866,37 @@ def bench_serve(args, P, W, np, torch, dev):
             for t, st, _ in S.collect():
                 i = pending.pop(t)
                 fin = time.perf_counter() - t0
-                lat.append(fin - trace[i].t_arrival)
+                lat[i] = fin - trace[i].t_arrival
                 done_at.append(fin)
         span = max(done_at) - trace[0].t_arrival
-        lat_ms = np.asarray(lat) * 1e3
-        return {"requests": count, "slots": slots,
-                "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-                "dof_per_s": sum(dofs[:count]) / span, "span_s": round(span, 3)}
+        return lat, span
 
-    served = run(args.serve_slots, len(trace))
-    seq = run(1, min(len(trace), 500))
+    def summary(lat, span, idx):
+        if not idx:
+            return {"requests": 0}
+        ms = np.asarray([lat[i] for i in idx]) * 1e3
+        return {"requests": len(idx), "p50_ms": round(float(np.percentile(ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(ms, 99)), 3),
+                "dof_per_s": sum(dofs[i] for i in idx) / span}
+
+    lat, span = run(args.serve_slots, len(trace))
+    torch.cuda.synchronize()
+    ratios = [err_ratio(torch, outs[i], r.level, r.modes, r.ndim, dev) for i, r in enumerate(trace)]
+    ok = [i for i, q in enumerate(ratios) if q <= 1.1]
+    miss = [i for i, q in enumerate(ratios) if q > 1.1]
+    served = summary(lat, span, list(range(len(trace))))
+    served.update({"slots": args.serve_slots, "span_s": round(span, 3)})
+    at_disc = summary(lat, span, ok)
+    seq_n = min(len(trace), 500)
+    lat1, span1 = run(1, seq_n)
+    seq = summary(lat1, span1, list(range(seq_n)))
+    seq.update({"slots": 1, "span_s": round(span1, 3)})
     offered = sum(dofs) / trace[-1].t_arrival
+    by_w = {}
+    for w in sorted({r.w for r in trace}):
+        idx = [i for i, r in enumerate(trace) if r.w == w]
+        by_w[str(w)] = {"requests": len(idx), "at_disc_error": sum(ratios[i] <= 1.1 for i in idx),
+                        "worst_err_over_disc": round(max(ratios[i] for i in idx), 4)}
     # alone vs in the mix: re-solve a few requests one at a time
     same = True
     mix = [outs[i].clone() for i in range(8)]
@@ -799,9 +910,16 @@ def bench_serve(args, P, W, np, torch, dev):
     for i in range(8):
         same = same and bool(torch.equal(outs[i], mix[i]))
     return {"workload": f"{len(trace)} requests, Poisson arrivals at 2000/s (seed 2), 50% 2D "
-                        "sides 65..1025, 50% 3D sides 33..129, w in {8,16,24,32}, FMG with "
-                        "N=max(2,L-3) IR-V(1,0)", "offered_dof_per_s": offered,
-            "server": served, "sequential_one_slot": seq,
+                        "sides 65..1025, 50% 3D sides 33..129, w in {8,16,24,32} (the inner "
+                        "width on every level), FMG with N IR-V(1,0) per level, N calibrated "
+                        "per (dim, level, w) to reach the discretization error",
+            "schedule_N": {f"{c[0]}D L{c[1]} w{c[2]}": (v[0] if v[0] else "unreached")
+                           for c, v in sched.items()},
+            "calibration_s": round(calib_s, 2),
+            "offered_dof_per_s": offered,
+            "server": served, "server_at_disc_error": at_disc,
+            "requests_missing_disc_error": len(miss), "by_w": by_w,
+            "sequential_one_slot": seq,
             "speedup_dof_per_s": round(served["dof_per_s"] / seq["dof_per_s"], 2),
             "alone_equals_mix": same}
 

@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--loop-sample", type=int, default=32,
                     help="problems solved one at a time for the batched comparison")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (no mg_autotune before timing)")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="oracle processes of the CPU baseline (at most the cores available)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the diagnostics, fallback and precision-estimation legs")
     ap.add_argument("--level3d", type=int, default=9, help="3D solve level (0: skip)")
@@ -181,6 +185,9 @@ def main():
         return err / disc
 
     # ---------------------------------------------------------- main run --
+    # per-level launch shapes of the star and transfer kernels, chosen by
+    # the library's autotuner on this hierarchy (results do not depend on them)
+    tune = H.autotune(reps=10, stream=stream) if not args.no_autotune else None
     xout = P.Vec(2, n, H.get_vec(L, 0).w, 32)
     ms = timed(H, xout, args.steps, args.warmup)
     ratio = accuracy(xout)
@@ -315,21 +322,7 @@ def main():
     # ---------------------------------------------------- CPU baseline ----
     cpu = None
     if not args.no_cpu:
-        from fractions import Fraction
-
-        from oracle import mg as omg
-        Lc = args.cpu_level
-        fo = {j: W.manufactured_f(j, 2) for j in range(1, Lc + 1)}
-        O = omg.build_hierarchy(fo, 2, Lc, omg.widths_progressive(Lc, args.w),
-                                omg.make_smoother(2, Fraction(23, 100)), policy="nn_ir_first_q")
-        t0 = time.perf_counter()
-        omg.fmg(O, 2)
-        t = time.perf_counter() - t0
-        ndof = ((1 << Lc) - 1) ** 2
-        cpu = {"value": ndof / t, "unit": "DoF/s", "cores": 1, "kind": "oracle",
-               "sample": f"one FMG solve of the same method on the {(1 << Lc) + 1}^2 grid "
-                         f"({Lc} levels, finest inner width {args.w}), exact Python integers, "
-                         f"{t:.1f} s"}
+        cpu = cpu_baseline(args.cpu_level, args.w, args.cpu_workers)
 
     traffic = None
     try:
@@ -368,7 +361,14 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_star2d (5-point residual A x - b, int32, finest level)",
                      "avg_us": round(kern_us, 2), "bytes_per_launch": kern_bytes},
-        "solve_algorithmic_gbs": step_bytes / (ms * 1e-3) / 1e9,
+        "solve_roofline": {"bound": "hbm", "achieved": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "bytes_per_step": step_bytes,
+                           "what": "every input of every quantized operation of the step read "
+                                   "once and every output written once (qcomp's second read "
+                                   "and halo re-reads not counted), over the step time"},
+        "autotune": tune,
         "fp64_mg_comparator": fp64,
         "bfp_over_fp64_dof_per_s": round((dof / (ms * 1e-3)) / fp64["dof_per_s"], 2),
         "stencil_apply": stencils,
@@ -383,6 +383,40 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def _oracle_fmg(level, w):
+    """One oracle FMG solve (test infrastructure: the CPU baseline only)."""
+    from fractions import Fraction
+
+    import workloads as W
+    from oracle import mg as omg
+    fo = {j: W.manufactured_f(j, 2) for j in range(1, level + 1)}
+    O = omg.build_hierarchy(fo, 2, level, omg.widths_progressive(level, w),
+                            omg.make_smoother(2, Fraction(23, 100)), policy="nn_ir_first_q")
+    t0 = time.perf_counter()
+    omg.fmg(O, 2)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(level, w, workers):
+    """The oracle (exact Python integers, not tuned) on the host cores: one
+    FMG solve of the same method on the (2^level + 1)^2 grid per worker
+    process, all workers at once; DoF/s = the workers' fine-grid unknowns
+    over the wall time."""
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    k = max(1, min(workers, cores))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(k) as pool:
+        secs = pool.starmap(_oracle_fmg, [(level, w)] * k)
+    wall = time.perf_counter() - t0
+    ndof = ((1 << level) - 1) ** 2
+    return {"value": k * ndof / wall, "unit": "DoF/s", "cores": k, "kind": "oracle",
+            "sample": f"{k} concurrent oracle FMG solves (one per process and core) of the same "
+                      f"method on the {(1 << level) + 1}^2 grid ({level} levels, finest inner "
+                      f"width {w}), exact Python integers; {wall:.1f} s wall, "
+                      f"{min(secs):.1f}-{max(secs):.1f} s per solve; {cores} cores available"}
 
 
 def bench_batch(args, P, W, np, torch, dev, stream, ev):
@@ -464,68 +498,30 @@ def bench_batch(args, P, W, np, torch, dev, stream, ev):
 
 def bench_fp64(P, torch, f, L, us, h2, disc, stream, ev):
     """FP64 multigrid on the same GPU with the same schedule (FMG, N = 2
-    IR-V(1,0), the same Chebyshev coefficients, the scaled operators
-    A' = [1; -1/4], R' = P^T, bilinear P), written with plain torch tensor
-    ops: the floating-point comparator of the metric."""
+    IR-V(1,0), the same Chebyshev coefficients and scaled operators), the
+    library's hand-written HIP solver (fp64_mg_*): the floating-point
+    comparator of the metric."""
     prm = P.mg_params_init(2, L, 32, True, 1, 0, 2, P.MG_POLICY_NN_IR_FIRST_Q, 23)
-    c1 = prm.c1.m * 2.0 ** prm.c1.exp
-    c2 = prm.c2.m * 2.0 ** prm.c2.exp
-    b = [None] + [f[j] * (2.0 ** (-2 * j) / 4.0) for j in range(1, L + 1)]
-
-    def A(x):
-        y = torch.zeros_like(x)
-        y[1:-1, 1:-1] = x[1:-1, 1:-1] - 0.25 * (x[:-2, 1:-1] + x[2:, 1:-1] + x[1:-1, :-2] + x[1:-1, 2:])
-        return y
-
-    def R(x):                        # fine (2n+1) -> coarse n, weights 2^-2 (4,2,1)
-        nc = (x.shape[0] - 3) // 2
-        c = torch.zeros((nc + 2, nc + 2), dtype=x.dtype, device=x.device)
-        e = slice(2, 2 * nc + 1, 2)
-        m = slice(1, 2 * nc, 2)
-        p_ = slice(3, 2 * nc + 2, 2)
-        c[1:-1, 1:-1] = (x[e, e] + 0.5 * (x[m, e] + x[p_, e] + x[e, m] + x[e, p_]) +
-                         0.25 * (x[m, m] + x[m, p_] + x[p_, m] + x[p_, p_]))
-        return c
-
-    def Pr(c):                       # coarse n -> fine 2n+1, bilinear
-        nc = c.shape[0] - 2
-        x = torch.zeros((2 * nc + 3, 2 * nc + 3), dtype=c.dtype, device=c.device)
-        x[0::2, 0::2] = c
-        x[1::2, 0::2] = 0.5 * (c[:-1, :] + c[1:, :])
-        x[:, 1::2] = 0.5 * (x[:, 0:-1:2] + x[:, 2::2])
-        x[0, :] = 0
-        x[-1, :] = 0
-        x[:, 0] = 0
-        x[:, -1] = 0
-        return x
-
-    def V(l, r):
-        y = c2 * A(r) + c1 * r
-        if l > 1:
-            d = V(l - 1, R(A(y) - r))
-            y = y - Pr(d)
-        return y
-
-    def fmg():
-        x = torch.zeros((3, 3), dtype=torch.float64, device=f[1].device)
-        for l in range(1, L + 1):
-            if l > 1:
-                x = Pr(x)
-            for _ in range(2):
-                x = x - V(l, A(x) - b[l])
-        return x
-
-    fmg()
+    F = P.FP64MG(prm)
+    out = torch.zeros(((1 << L) + 1,) * 2, dtype=torch.float64, device=us.device)
+    rhs = [f[j] for j in range(1, L + 1)]
+    for _ in range(3):
+        F.fmg(rhs, out, stream)
     torch.cuda.synchronize()
     e0, e1 = ev(), ev()
+    reps = 10
     e0.record(stream)
-    x = fmg()
+    for _ in range(reps):
+        F.fmg(rhs, out, stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    err = math.sqrt(float(((x - us)[1:-1, 1:-1] ** 2).sum()) * h2)
+    ms = e0.elapsed_time(e1) / reps
+    err = math.sqrt(float(((out - us)[1:-1, 1:-1] ** 2).sum()) * h2)
     dof = ((1 << L) - 1) ** 2
-    return {"what": "FP64 FMG, same schedule and coefficients, torch tensor ops on the same GPU",
+    del F, out
+    return {"what": "FP64 FMG, same schedule, coefficients and scaled operators, hand-written "
+                    "HIP kernels on the same GPU (fp64_mg_fmg; levels of <= 4096 points in one "
+                    "single-workgroup launch)",
             "ms": round(ms, 3), "dof_per_s": dof / (ms * 1e-3),
             "err_over_disc": round(err / disc, 4)}
 

@@ -513,6 +513,44 @@ int mg_server_collect(mg_server* s, uint64_t* tickets, mg_result* results, int c
 int mg_server_stats(const mg_server* s, int* queued, int* running, size_t* resident_bytes);
 int mg_server_destroy(mg_server* s);
 
+/* ---- FP64 multigrid comparator ----
+ * The same FMG schedule as the BFP solver (x_1 = 0, FMG prolongation, N
+ * IR-V(nu1, nu2) iterations per level, relaxation y = c2 A r + c1 r, the
+ * V-cycle of Appendix C with its added sweeps) on the same scaled operators,
+ * in IEEE double arithmetic on the GPU: the floating-point multigrid the
+ * BFP solves are compared with. c1, c2 are the coefficients for the stored
+ * operator (the doubles of mg_params.c1 / c2). Levels are dense padded
+ * FP64 grids in the caller's arena (fp64_mg_bytes).                      */
+typedef struct fp64_mg fp64_mg;
+size_t fp64_mg_bytes(int ndim, int L);   /* 0 on error */
+int fp64_mg_create(int ndim, int L, int nu1, int nu2, int N, double c1, double c2, void* arena_dev,
+                   size_t bytes, void* stream, fp64_mg** out);
+/* rhs_dev[j-1]: f_j on the padded level-j grid (as for mg_set_rhs);
+ * x_out_dev: dense (n_L + 2)^ndim doubles, the FMG solution.             */
+int fp64_mg_fmg(fp64_mg* h, const double* const* rhs_dev, double* x_out_dev, void* stream);
+int fp64_mg_destroy(fp64_mg* h);
+
+/* Launch-shape autotuning for the levels of h above its coarse-level
+ * executor: per level j, every march length of the star kernel (rows or
+ * planes per wave, 1..64) on the IR residual r = A x - b, and of the
+ * transfer kernels (coarse rows or planes per wave, 1..32) on the
+ * restriction into level j - 1 plus the prolongation-correction from it,
+ * is timed on `stream` with HIP events (median of three runs of `reps`
+ * back-to-back launches on h's own blocks); the fastest, when it beats the
+ * default shape, is kept in the process-wide per-level table that every
+ * later launch on grids of that size uses (an explicit tuning key still
+ * takes precedence). Results never depend on launch shapes. Overwrites h's
+ * work blocks (r, s, t, the restricted residuals): set the right-hand side
+ * again before solving. Synchronizes `stream`. out (nullable) receives the
+ * chosen shapes (0 = default kept) and the times.                        */
+typedef struct {
+  int32_t first_level, last_level;
+  int32_t star_rows[MG_MAX_LEVELS + 1], transfer_rows[MG_MAX_LEVELS + 1];
+  float star_us[MG_MAX_LEVELS + 1], star_default_us[MG_MAX_LEVELS + 1];
+  float transfer_us[MG_MAX_LEVELS + 1], transfer_default_us[MG_MAX_LEVELS + 1];
+} mg_tune_report;
+int mg_autotune(mg_hierarchy* h, int reps, void* stream, mg_tune_report* out);
+
 /* Launch-shape tuning (process-wide; results do not depend on it):
  * "star2d_rows" / "star3d_rows" = rows or planes one wave of the star
  * stencil kernels marches on large grids, "star2d_small_n" /
@@ -521,7 +559,8 @@ int mg_server_destroy(mg_server* s);
  * rounded down to a power of two in [1, 64]); "transfer_rows" = coarse
  * rows (2D) or planes (3D) one wave of the restriction / prolongation
  * kernels marches (0, the default: a power of two in [1, 32] that gives a
- * few thousand waves); "exec_max_points" = largest grid (in interior points) whose
+ * few thousand waves); "level_rows_clear" (any value) forgets the per-level
+ * shapes mg_autotune chose; "exec_max_points" = largest grid (in interior points) whose
  * level runs inside the one-workgroup coarse-level programs a hierarchy
  * records at creation (0 = never; read by mg_hierarchy_bytes/create);
  * "diagnostics" = 1: hierarchies created while it is set keep the solve

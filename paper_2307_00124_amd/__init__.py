@@ -385,6 +385,63 @@ class Hierarchy:
         check(lib.mg_counters(self.h, C.byref(b), C.byref(n)), "mg_counters")
         return b.value, n.value
 
+    def autotune(self, reps: int = 20, stream=None) -> dict:
+        """mg_autotune: per-level launch shapes of the star and transfer
+        kernels, timed on this hierarchy (overwrites its work blocks)."""
+        r = abi.mg_tune_report()
+        check(lib.mg_autotune(self.h, reps, _stream(stream), C.byref(r)), "mg_autotune")
+        out = {}
+        for j in range(r.first_level, r.last_level + 1):
+            out[j] = {"star_rows": r.star_rows[j] or "default",
+                      "star_us": round(r.star_us[j], 2),
+                      "star_default_us": round(r.star_default_us[j], 2)}
+            if j >= 2:
+                out[j].update({"transfer_rows": r.transfer_rows[j] or "default",
+                               "transfer_us": round(r.transfer_us[j], 2),
+                               "transfer_default_us": round(r.transfer_default_us[j], 2)})
+        return out
+
+
+class FP64MG:
+    """The FP64 multigrid comparator (fp64_mg_* calls) for a BFP schedule:
+    same shape, cycle, N and Chebyshev coefficients."""
+
+    def __init__(self, params: abi.mg_params, device="cuda", stream=None):
+        self.params = params
+        nbytes = lib.fp64_mg_bytes(params.ndim, params.L)
+        if nbytes == 0:
+            raise BFPError(abi.BFP_EINVAL, "fp64_mg_bytes")
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.arena.data_ptr()) % 256
+        self.arena = self.arena[off:off + nbytes]
+        c1 = params.c1.m * 2.0 ** params.c1.exp
+        c2 = params.c2.m * 2.0 ** params.c2.exp
+        h = C.c_void_p()
+        check(lib.fp64_mg_create(params.ndim, params.L, params.nu1, params.nu2, params.N, c1, c2,
+                                 _ptr(self.arena), nbytes, _stream(stream), C.byref(h)),
+              "fp64_mg_create")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and lib is not None:
+            lib.fp64_mg_destroy(h)
+            self.h = None
+
+    def fmg(self, rhs: list, out: torch.Tensor, stream=None) -> torch.Tensor:
+        L = self.params.L
+        if len(rhs) != L:
+            raise ValueError(f"need {L} right-hand sides, got {len(rhs)}")
+        side = (1 << L) + 1
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != side ** self.params.ndim:
+            raise ValueError("out must be a contiguous float64 tensor of the padded finest grid")
+        for j, f in enumerate(rhs, start=1):
+            if f.dtype != torch.float64 or not f.is_contiguous() or f.numel() != ((1 << j) + 1) ** self.params.ndim:
+                raise ValueError(f"rhs[{j - 1}] must hold the padded level-{j} grid in float64")
+        self._ptrs = (C.c_void_p * L)(*[f.data_ptr() for f in rhs])
+        check(lib.fp64_mg_fmg(self.h, self._ptrs, _ptr(out), _stream(stream)), "fp64_mg_fmg")
+        return out
+
 
 class Batch:
     """Independent problems solved together (mg_batch_* calls): one arena,

@@ -62,6 +62,16 @@ class mg_prec_est_result(C.Structure):
                 ("rho", C.c_double), ("rates", C.c_int32)]
 
 
+_LF = C.c_float * (MG_MAX_LEVELS + 1)
+
+
+class mg_tune_report(C.Structure):
+    _fields_ = [("first_level", C.c_int32), ("last_level", C.c_int32),
+                ("star_rows", _W), ("transfer_rows", _W),
+                ("star_us", _LF), ("star_default_us", _LF),
+                ("transfer_us", _LF), ("transfer_default_us", _LF)]
+
+
 class mg_server_cfg(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32),
                 ("exec_max_points", C.c_int32)]
@@ -136,6 +146,11 @@ SIGNATURES = {
     "mg_server_stats": (I, [VP, P(I), P(I), P(C.c_size_t)]),
     "mg_server_collect": (I, [VP, P(C.c_uint64), P(mg_result), I, P(I)]),
     "mg_server_destroy": (I, [VP]),
+    "mg_autotune": (I, [VP, I, VP, P(mg_tune_report)]),
+    "fp64_mg_bytes": (C.c_size_t, [I, I]),
+    "fp64_mg_create": (I, [I, I, I, I, I, C.c_double, C.c_double, VP, C.c_size_t, VP, P(VP)]),
+    "fp64_mg_fmg": (I, [VP, VP, VP, VP]),
+    "fp64_mg_destroy": (I, [VP]),
     "bfp_tuning_set": (I, [C.c_char_p, I]),
     "bfp_tuning_get": (I, [C.c_char_p, C.POINTER(I)]),
     "bfp_last_error": (C.c_char_p, []),

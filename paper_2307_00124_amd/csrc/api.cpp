@@ -50,6 +50,12 @@ static thread_local int64_t* g_diag = nullptr;
 
 void set_diag_row(int64_t* row) { g_diag = row; }
 
+// While set (on this host thread), the operations reduce their outputs
+// through these per-block slots (2 * kMaxSlotBlocks int64).
+static thread_local int64_t* g_slots = nullptr;
+
+void set_slots(int64_t* slots) { g_slots = slots; }
+
 static int64_t out_n(const StarLaunch& l) { return l.n; }
 static int64_t out_n(const TransferLaunch& l) { return l.n_out; }
 static int64_t out_n(const PointLaunch& l) { return l.n; }
@@ -105,8 +111,32 @@ int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas) {
 // default aims at a few thousand waves per launch (0 = default).
 static int g_transfer_rows = 0;
 
+// Per-level shapes chosen by mg_autotune, [ndim - 2][level j] for grids of
+// n = 2^j - 1 points per dimension (transfers: the fine grid's level); 0 =
+// the default. An explicit tuning key takes precedence.
+static int g_level_rows[2][2][MG_MAX_LEVELS + 1];   // [kind: star, transfer]
+
+static int pow2_level(int64_t n) {
+  for (int j = 1; j <= MG_MAX_LEVELS; ++j)
+    if (n == ((int64_t)1 << j) - 1) return j;
+  return 0;
+}
+
+void set_level_rows(int kind, int ndim, int level, int rows) {
+  if ((kind == 0 || kind == 1) && (ndim == 2 || ndim == 3) && level >= 1 && level <= MG_MAX_LEVELS)
+    g_level_rows[kind][ndim - 2][level] = rows;
+}
+
+int level_rows(int kind, int ndim, int level) {
+  if ((kind == 0 || kind == 1) && (ndim == 2 || ndim == 3) && level >= 1 && level <= MG_MAX_LEVELS)
+    return g_level_rows[kind][ndim - 2][level];
+  return 0;
+}
+
 static int transfer_rows(int ndim, int64_t n_out, int64_t nc) {
   if (g_transfer_rows > 0) return g_transfer_rows;
+  const int tuned = level_rows(1, ndim, pow2_level(2 * nc + 1));
+  if (tuned > 0) return tuned;
   const int64_t segs = (n_out + 2 + 255) / 256;
   const int64_t lines = ndim == 2 ? segs * (nc + 1) : segs * (nc + 1) * (nc + 1);
   int rows = 1;
@@ -115,13 +145,16 @@ static int transfer_rows(int ndim, int64_t n_out, int64_t nc) {
 }
 
 static int star_rows(int ndim, int64_t n) {
+  const int tuned = level_rows(0, ndim, pow2_level(n));
   if (ndim == 2) {
     if (g_star2d_rows_large > 0) return n < g_star2d_small_n ? 1 : g_star2d_rows_large;
+    if (tuned > 0) return tuned;
     int64_t r = n * n / (1 << 18);
     int rows = 1;
     while (rows * 2 <= r && rows < 64) rows *= 2;
     return rows;
   }
+  if (tuned > 0 && g_star3d_rows_large == 32 && g_star3d_small_n == 64) return tuned;
   return n < g_star3d_small_n ? 1 : g_star3d_rows_large;
 }
 
@@ -267,6 +300,7 @@ static void fill_common(OpArgs* op, int w_out, const bfp_vec* x, const bfp_vec* 
   op->lo = -((int64_t)1 << (w_out - 1));
   op->hi = ((int64_t)1 << (w_out - 1)) - 1;
   op->diag = g_diag;
+  op->slots = g_slots;
 }
 
 // Run one op in the requested mode: nnqcomp in one launch, qcomp as the
@@ -612,6 +646,10 @@ int bfp_tuning_set(const char* key, int value) {
   // 2D: rows 0 restores the size heuristic (then small_n is not read)
   if (k == "star2d_rows") { g_star2d_rows_large = value; return BFP_OK; }
   if (k == "transfer_rows") { g_transfer_rows = value; return BFP_OK; }
+  if (k == "level_rows_clear") {   // forget the shapes mg_autotune chose
+    std::memset(g_level_rows, 0, sizeof g_level_rows);
+    return BFP_OK;
+  }
   if (k == "star2d_small_n") { g_star2d_small_n = value; return BFP_OK; }
   if (value < 1) return fail(BFP_EINVAL, "value out of range");
   if (k == "star3d_rows") g_star3d_rows_large = value;

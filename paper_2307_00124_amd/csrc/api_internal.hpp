@@ -37,6 +37,9 @@ bool recording();
 // Diagnostic counters (kDiagBins) that the next operations issued on this
 // host thread count into; null turns the counting off.
 void set_diag_row(int64_t* row);
+// Per-block reduction slots (2 * kMaxSlotBlocks int64) the next operations
+// issued on this host thread use; null: the output's accumulator sets.
+void set_slots(int64_t* slots);
 // Whether hierarchies created now keep diagnostics (tuning key "diagnostics").
 bool diagnostics_on();
 // grids of at most this many points run inside recorded programs (0: never)
@@ -64,6 +67,15 @@ int hierarchy_create_ex(const mg_params* prm, void* arena_dev, size_t bytes, voi
 // Chebyshev coefficients c1, c2, c1_gamma of p for eta = eta_percent / 100
 // (rho = 2, rescaled to the stored operator, 16-bit)
 int set_smoother(mg_params* p, int eta_percent);
+
+// Per-level launch shapes (kind 0: star stencils, rows / planes per wave;
+// kind 1: grid transfers, coarse rows / planes per wave, keyed by the fine
+// level); 0 restores the default.
+void set_level_rows(int kind, int ndim, int level, int rows);
+int level_rows(int kind, int ndim, int level);
+
+// mg_fmg_f64 on one stream (no side stream), same results
+int fmg_f64_one_stream(mg_hierarchy* h, const double* const* rhs_dev, hipStream_t s);
 
 // validation of multigrid parameters (BFP_OK or the error of mg_params checks)
 int params_ok(const mg_params* p);

@@ -64,7 +64,12 @@ struct OpArgs {
   int64_t assign_exp;       // kModeAssign only
   int abits, bbits;         // |alpha S x| < 2^abits and |beta y| < 2^bbits
   int64_t* diag;            // kDiagBins diagnostic counters of the op's call site, or null
+  int64_t* slots;           // 2 * kMaxSlotBlocks int64 of per-block partials for the
+                            // output reduction, or null (z's accumulator sets)
 };
+
+// Launches with at most this many blocks may reduce through per-block slots.
+constexpr int kMaxSlotBlocks = 8192;
 
 // A padded, row-pitched grid: rows = (n+2)^(ndim-1) rows of `pitch` elements.
 struct Grid {

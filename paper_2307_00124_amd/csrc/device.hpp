@@ -338,6 +338,105 @@ __device__ __forceinline__ void finish_mu(int64_t tmu, int64_t* zm) {
   }
 }
 
+// Reductions through per-block slots (a caller-provided array of 2 int64
+// per block, e.g. one per solver hierarchy): thread 0 of every block
+// exchanges its packed partial into its own slots (no two blocks touch the
+// same address, so nothing queues behind other blocks' atomics), then
+// takes the two-level ticket; in the block that finishes last, one wave
+// reads all slots at once (independent atomics, one round trip) and
+// publishes the result. Every slot [0, blocks) is written by each launch
+// before its ticket, so no reset is needed.
+__device__ __forceinline__ void finish_outputs_slots(int64_t tmax, int64_t tmin, int64_t tsat,
+                                                     int64_t* zm, int64_t* slots, int64_t e_out) {
+  __shared__ int32_t s_red[3][kBlock / 64];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  const int32_t a = wave_max32((int32_t)tmax), b = wave_min32((int32_t)tmin),
+                c = wave_sum32((int32_t)tsat);
+  if ((tid & 63) == 0) {
+    s_red[0][tid >> 6] = a;
+    s_red[1][tid >> 6] = b;
+    s_red[2][tid >> 6] = c;
+  }
+  __syncthreads();
+  const unsigned nblk = gridDim.x * gridDim.y * gridDim.z;
+  if (tid == 0) {
+    int32_t bmax = s_red[0][0], bmin = s_red[1][0];
+    int64_t bsat = s_red[2][0];
+    for (int i = 1; i < kBlock / 64; ++i) {
+      bmax = s_red[0][i] > bmax ? s_red[0][i] : bmax;
+      bmin = s_red[1][i] < bmin ? s_red[1][i] : bmin;
+      bsat += s_red[2][i];
+    }
+    if (nblk == 1) {
+      zm[kMetaMax] = bmax;
+      zm[kMetaMin] = bmin;
+      zm[kMetaSat] = bsat;
+      zm[kMetaExp] = e_out;
+      s_last = 0;
+    } else {
+      const unsigned blk = block_linear();
+      const uint64_t packed = ((uint64_t)(uint32_t)bmax << 32) | (uint32_t)bmin;
+      const int64_t r = axch(&slots[2 * blk], (int64_t)packed) ^ axch(&slots[2 * blk + 1], bsat);
+      s_last = take_ticket(zm, r);
+    }
+  }
+  __syncthreads();
+  if (!s_last || tid >= 64) return;
+  int32_t mx = 0, mn = 0;
+  int64_t st = 0;
+  for (unsigned k = tid; k < nblk; k += 64) {
+    const uint64_t p = (uint64_t)axch(&slots[2 * k], 0);
+    const int32_t hmax = (int32_t)(uint32_t)(p >> 32), hmin = (int32_t)(uint32_t)p;
+    mx = hmax > mx ? hmax : mx;
+    mn = hmin < mn ? hmin : mn;
+    st += axch(&slots[2 * k + 1], 0);
+  }
+  mx = wave_max32(mx);
+  mn = wave_min32(mn);
+  st = wave_sum(st);
+  if (tid == 0) {
+    axch(&zm[kMetaTicket], 0);
+    zm[kMetaMax] = mx;
+    zm[kMetaMin] = mn;
+    zm[kMetaSat] = st;
+    zm[kMetaExp] = e_out;
+  }
+}
+
+// First qcomp pass through slots: mu* = max(1, max of the blocks' mu).
+__device__ __forceinline__ void finish_mu_slots(int64_t tmu, int64_t* zm, int64_t* slots) {
+  __shared__ int32_t s_red[kBlock / 64];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  const int32_t m = wave_max32((int32_t)tmu);
+  if ((tid & 63) == 0) s_red[tid >> 6] = m;
+  __syncthreads();
+  const unsigned nblk = gridDim.x * gridDim.y * gridDim.z;
+  if (tid == 0) {
+    int32_t b = s_red[0];
+    for (int i = 1; i < kBlock / 64; ++i) b = s_red[i] > b ? s_red[i] : b;
+    if (nblk == 1) {
+      zm[kMetaMu] = b < 1 ? 1 : b;
+      s_last = 0;
+    } else {
+      s_last = take_ticket(zm, axch(&slots[2 * block_linear()], b));
+    }
+  }
+  __syncthreads();
+  if (!s_last || tid >= 64) return;
+  int32_t mu = 1;
+  for (unsigned k = tid; k < nblk; k += 64) {
+    const int32_t v = (int32_t)axch(&slots[2 * k], 0);
+    mu = v > mu ? v : mu;
+  }
+  mu = wave_max32(mu);
+  if (tid == 0) {
+    axch(&zm[kMetaTicket], 0);
+    zm[kMetaMu] = mu;
+  }
+}
+
 // --------------------------------------------------------- op planning --
 
 // Everything a kernel derives once (uniformly) from the metadata of its

@@ -129,6 +129,7 @@ struct Epi {
   int32_t tmax, tmin;
   int64_t tmu;
   int64_t* zm;
+  int64_t* slots;  // per-block partials of the reduction (or null)
   int64_t* diag;   // the call site's diagnostic counters (or null)
   int dbin;        // qcomp window-gap bin to count, or -1
   int dsat;        // 1: count an nnqcomp call and its saturations
@@ -143,6 +144,7 @@ struct Epi {
     lo = op.lo;
     hi = op.hi;
     zm = op.z_meta;
+    slots = op.slots;
     swap = R.ea < R.eb;
     D = swap ? R.eb - R.ea : R.ea - R.eb;
     const int64_t la = R.sa, lb = R.eb - R.eo;
@@ -245,6 +247,11 @@ struct Epi {
   }
 
   __device__ __forceinline__ void finish() {
+    if (slots) {
+      if (PASS == kQ1) finish_mu_slots(tmu, zm, slots);
+      else finish_outputs_slots(tmax, tmin, tsat, zm, slots, R.eo);
+      return;
+    }
     if (PASS == kQ1) finish_mu(tmu, zm);
     else finish_outputs(tmax, tmin, tsat, zm, R.eo);
   }

@@ -74,6 +74,10 @@ struct mg_hierarchy {
   // diagnostic counters [level 0..MG_MAX_LEVELS][site][kDiagBins] in the
   // arena (null for hierarchies that keep none, e.g. the batched ones)
   int64_t* diag = nullptr;
+  // per-block partials of the launched operations' output reductions
+  // (2 * kMaxSlotBlocks int64; null for batched hierarchies, whose
+  // operations all run inside one workgroup)
+  int64_t* slots = nullptr;
   // mg_fmg_f64: a second stream (created on first use) that quantizes the
   // finer levels' right-hand sides while the program runs the coarse ones
   hipStream_t side = nullptr;
@@ -186,12 +190,17 @@ int level_of(int64_t n) {
   while (((int64_t)1 << j) - 1 < n) ++j;
   return j;
 }
+// ... and the hierarchy's per-block reduction slots
 struct DiagScope {
   DiagScope(mg_hierarchy* h, Site site, int64_t n) {
     set_diag_row(h->diag ? h->diag + ((int64_t)level_of(n) * kDiagSites + site) * kDiagBins
                          : nullptr);
+    set_slots(h->slots);
   }
-  ~DiagScope() { set_diag_row(nullptr); }
+  ~DiagScope() {
+    set_diag_row(nullptr);
+    set_slots(nullptr);
+  }
 };
 
 int op_stencil(mg_hierarchy* h, const bfp_stencil* S, const bfp_vec& x, const bfp_scalar* al,
@@ -201,10 +210,11 @@ int op_stencil(mg_hierarchy* h, const bfp_stencil* S, const bfp_vec& x, const bf
   int rc = stencil_apply_impl(S, &x, al, be, y, z.w, mode, &g, &z, s, 0);
   if (rc) return rc;
   const int passes = mode == BFP_NORMALIZE ? 2 : 1;
-  // algorithmic bytes: every input read once (y = x, the relaxation, once)
+  // algorithmic bytes: every input read once (y = x, the relaxation, once;
+  // qcomp's second read pass is overhead, not counted), the output written once
   const bool y_own = y && y->mant != x.mant;
   const double rd = pts(x) * sz(x) + (y_own ? pts(*y) * sz(*y) : 0.0);
-  h->bytes += passes * rd + pts(z) * sz(z);
+  h->bytes += rd + pts(z) * sz(z);
   h->launches += passes;
   return BFP_OK;
 }
@@ -215,7 +225,7 @@ int op_sub(mg_hierarchy* h, const bfp_vec& x, const bfp_vec& y, bfp_vec& z, Site
   int rc = point_impl(&kOne, &x, &kMinusOne, &y, z.w, mode, &g, &z, s, -1);
   if (rc) return rc;
   const int passes = mode == BFP_NORMALIZE ? 2 : 1;
-  h->bytes += passes * (pts(x) * sz(x) + pts(y) * sz(y)) + pts(z) * sz(z);
+  h->bytes += pts(x) * sz(x) + pts(y) * sz(y) + pts(z) * sz(z);
   h->launches += passes;
   return BFP_OK;
 }
@@ -414,7 +424,8 @@ int check_params(const mg_params* p) {
 // Lay out (or only size) every level's blocks in the arena, followed by
 // room for `nops` recorded operations.
 // diag: also reserve the diagnostic counters (h->diag) after the programs
-size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops, bool diag) {
+size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops, bool diag,
+              bool slots = true) {
   size_t off = 0;
   const int mb = p->min_storage_bits;
   for (int j = 1; j <= p->L; ++j) {
@@ -449,6 +460,11 @@ size_t layout(mg_hierarchy* h, const mg_params* p, char* base, size_t nops, bool
   if (diag) {
     h->diag = base ? (int64_t*)(base + off) : nullptr;
     off = align256(off + kDiagBytes);
+  }
+  h->slots = nullptr;
+  if (slots) {
+    h->slots = base ? (int64_t*)(base + off) : nullptr;
+    off = align256(off + 2 * (size_t)kMaxSlotBlocks * sizeof(int64_t));
   }
   return off;
 }
@@ -603,7 +619,7 @@ int plan_batch(mg_batch* B, const mg_params* prms, int nprob, char* arena, size_
       BatchGroup& G = B->groups.back();
       if ((rc = setup(G.h, &G.prm, 0))) return rc;
       G.h->Lc = 0;
-      G.region = layout(G.h, &G.prm, reinterpret_cast<char*>(kStandIn), 0, false);
+      G.region = layout(G.h, &G.prm, reinterpret_cast<char*>(kStandIn), 0, false, false);
       if ((rc = record_batch_program(G))) return rc;
     }
     B->group_of[i] = gi;
@@ -955,6 +971,129 @@ int mg_fmg_f64(mg_hierarchy* h, const double* const* rhs_dev, void* stream) {
   if ((rc = run_program(h, pc, s, &r))) return rc;
   if (Lc < L && (rc = hip_check(hipStreamWaitEvent(s, h->join, 0), "stream wait"))) return rc;
   return fmg_levels(h, Lc + 1, L, s);
+}
+
+}  // extern "C"
+
+// mg_fmg_f64 with every step on `stream` (no second stream): the finer
+// levels' right-hand sides are quantized before the coarse-level program
+// runs. The same blocks as mg_fmg_f64.
+int bfpk::fmg_f64_one_stream(mg_hierarchy* h, const double* const* rhs_dev, hipStream_t s) {
+  if (!h || !rhs_dev) return fail(BFP_EINVAL, "NULL argument");
+  const int L = h->prm.L, Lc = h->Lc;
+  for (int j = 1; j <= L; ++j)
+    if (!rhs_dev[j - 1]) return fail(BFP_EINVAL, "right-hand side of level %d is NULL", j);
+  int rc;
+  const Program& pc = h->prog[kPFc];
+  if (!pc.count) {
+    for (int j = 1; j <= L; ++j)
+      if ((rc = mg_set_rhs(h, j, rhs_dev[j - 1], s))) return rc;
+    return mg_fmg(h, s);
+  }
+  for (int j = Lc + 1; j <= L; ++j)
+    if ((rc = mg_set_rhs(h, j, rhs_dev[j - 1], s))) return rc;
+  ExecRhs r{};
+  for (int j = 1; j <= L; ++j) r.p[j - 1] = rhs_dev[j - 1];
+  if ((rc = run_program(h, pc, s, &r))) return rc;
+  return fmg_levels(h, Lc + 1, L, s);
+}
+
+extern "C" {
+
+int mg_autotune(mg_hierarchy* h, int reps, void* stream, mg_tune_report* out) {
+  if (!h) return fail(BFP_EINVAL, "NULL hierarchy");
+  if (reps < 1 || reps > 1000) return fail(BFP_EINVAL, "reps must be in 1..1000");
+  hipStream_t s = (hipStream_t)stream;
+  const int nd = h->prm.ndim, L = h->prm.L;
+  const double b0 = h->bytes;
+  const int64_t l0 = h->launches;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_check(hipEventCreate(&e0), "event");
+  if (!rc) rc = hip_check(hipEventCreate(&e1), "event");
+  mg_tune_report rep;
+  std::memset(&rep, 0, sizeof rep);
+  rep.first_level = h->Lc + 1;
+  rep.last_level = L;
+  // average time of `reps` back-to-back launches of op(), median of three
+  auto timed = [&](auto op, float* us) {
+    float t[3];
+    for (int k = 0; k < 3 && !rc; ++k) {
+      for (int i = 0; i < 2 && !rc; ++i) rc = op();
+      if (!rc) rc = hip_check(hipEventRecord(e0, s), "event record");
+      for (int i = 0; i < reps && !rc; ++i) rc = op();
+      if (!rc) rc = hip_check(hipEventRecord(e1, s), "event record");
+      if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
+      float ms = 0;
+      if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+      t[k] = ms * 1000.0f / reps;
+    }
+    if (rc) return;
+    std::sort(t, t + 3);
+    *us = t[1];
+  };
+  const int cands[] = {1, 2, 4, 8, 16, 32, 64};
+  for (int j = h->Lc + 1; j <= L && !rc; ++j) {
+    Level& V = h->lv[j];
+    // the IR residual r = A x - b (the star kernel with a y stream)
+    auto star = [&]() {
+      return op_stencil(h, &h->A, V.x, &kOne, &kMinusOne, &V.b, V.r, kIrRes, BFP_SATURATE,
+                        g_norm(V.r, kOne), s);
+    };
+    float best = 0, t = 0;
+    int pick = 0;
+    set_level_rows(0, nd, j, 0);
+    timed(star, &rep.star_default_us[j]);
+    for (int c : cands) {
+      if (rc || c > V.n) break;
+      set_level_rows(0, nd, j, c);
+      timed(star, &t);
+      if (!rc && (!pick || t < best)) { best = t; pick = c; }
+    }
+    if (rc) break;
+    if (best < rep.star_default_us[j]) {
+      set_level_rows(0, nd, j, pick);
+      rep.star_rows[j] = pick;
+      rep.star_us[j] = best;
+    } else {
+      set_level_rows(0, nd, j, 0);
+      rep.star_us[j] = rep.star_default_us[j];
+    }
+    if (j < 2) continue;
+    // restriction s_j -> vr_(j-1) and prolongation-correction t_j = y_j - P y_(j-1)
+    Level& Cl = h->lv[j - 1];
+    auto transfer = [&]() {
+      int e = op_stencil(h, &h->R, V.s, &kOne, nullptr, nullptr, Cl.vr, kRestrict, BFP_SATURATE,
+                         g_norm(V.s, kFour), s);
+      if (e) return e;
+      return op_stencil(h, &h->P, Cl.y, &kMinusOne, &kOne, &V.y, V.t, kVCorr, BFP_SATURATE,
+                        g_sum(V.y, Cl.y), s);
+    };
+    best = 0;
+    pick = 0;
+    set_level_rows(1, nd, j, 0);
+    timed(transfer, &rep.transfer_default_us[j]);
+    for (int c : cands) {
+      if (rc || c > 32 || c > Cl.n + 1) break;
+      set_level_rows(1, nd, j, c);
+      timed(transfer, &t);
+      if (!rc && (!pick || t < best)) { best = t; pick = c; }
+    }
+    if (rc) break;
+    if (best < rep.transfer_default_us[j]) {
+      set_level_rows(1, nd, j, pick);
+      rep.transfer_rows[j] = pick;
+      rep.transfer_us[j] = best;
+    } else {
+      set_level_rows(1, nd, j, 0);
+      rep.transfer_us[j] = rep.transfer_default_us[j];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->bytes = b0;
+  h->launches = l0;
+  if (!rc && out) *out = rep;
+  return rc;
 }
 
 int mg_diag_read(mg_hierarchy* h, int64_t* host_out, int reset, void* stream) {

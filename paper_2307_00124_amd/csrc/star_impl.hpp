@@ -266,13 +266,15 @@ __global__ __launch_bounds__(kBlock) void k_star3d(const StarLaunch L) {
 // ----------------------------------------------------------- launchers --
 
 template <typename TX, typename TY, typename TZ, int PASS, bool HASY, bool YX = false>
-static hipError_t star_go(const StarLaunch& L, hipStream_t s) {
+static hipError_t star_go(const StarLaunch& L0, hipStream_t s) {
+  StarLaunch L = L0;
   const int64_t n = L.n;
   const int rows = L.rows > 0 ? L.rows : 1;
   if (L.ndim == 2) {
     const int64_t segs = (n + 1 + 255) / 256, bands = (n + rows - 1) / rows;
     const int wx = L.wx;
     dim3 grid((unsigned)((segs + wx - 1) / wx), (unsigned)((bands + 4 / wx - 1) / (4 / wx)));
+    if ((int64_t)grid.x * grid.y > kMaxSlotBlocks) L.op.slots = nullptr;
     if (rows >= 4 && rows % 4 == 0) {
       if (L.wide)
         hipLaunchKernelGGL((k_star2d<TX, TY, TZ, PASS, HASY, true, 4, YX>), grid, dim3(kBlock), 0, s, L);
@@ -287,6 +289,7 @@ static hipError_t star_go(const StarLaunch& L, hipStream_t s) {
   } else {
     dim3 grid((unsigned)((n + 1 + 255) / 256), (unsigned)((n + 4 * kYS - 1) / (4 * kYS)),
               (unsigned)((n + rows - 1) / rows));
+    if ((int64_t)grid.x * grid.y * grid.z > kMaxSlotBlocks) L.op.slots = nullptr;
     hipLaunchKernelGGL((k_star3d<TX, TY, TZ, PASS, HASY, YX>), grid, dim3(kBlock), 0, s, L);
   }
   return hipGetLastError();

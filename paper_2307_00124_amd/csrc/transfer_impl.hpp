@@ -348,12 +348,14 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const TransferLaunch L) {
 // ----------------------------------------------------------- launches ---
 
 template <int ND, typename TX, typename TY, typename TZ, int PASS, bool HASY>
-static hipError_t transfer_go(const TransferLaunch& L, hipStream_t s) {
+static hipError_t transfer_go(const TransferLaunch& L0, hipStream_t s) {
+  TransferLaunch L = L0;
   const int rows = L.rows > 0 ? L.rows : 1;
   if (L.kind == 1) {
     const int64_t nc = L.n_out;
     const int64_t segs = (nc + 2 + 255) / 256;
     const int64_t bands = ND == 3 ? nc * ((nc + rows - 1) / rows) : (nc + rows - 1) / rows;
+    if (segs * ((bands + 3) / 4) > kMaxSlotBlocks) L.op.slots = nullptr;
     hipLaunchKernelGGL((k_restrict<ND, TX, TY, TZ, PASS, HASY>),
                        dim3((unsigned)segs, (unsigned)((bands + 3) / 4)), dim3(kBlock), 0, s, L);
   } else {
@@ -361,6 +363,7 @@ static hipError_t transfer_go(const TransferLaunch& L, hipStream_t s) {
     const int64_t segs = (nf + 2 + 255) / 256;
     const int64_t nb = (nc + 1 + rows - 1) / rows;
     const int64_t bands = ND == 3 ? (nc + 1) * nb : nb;
+    if (segs * ((bands + 3) / 4) > kMaxSlotBlocks) L.op.slots = nullptr;
     hipLaunchKernelGGL((k_prolong<ND, TX, TY, TZ, PASS, HASY>),
                        dim3((unsigned)segs, (unsigned)((bands + 3) / 4)), dim3(kBlock), 0, s, L);
   }

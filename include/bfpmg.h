@@ -513,6 +513,26 @@ int mg_server_collect(mg_server* s, uint64_t* tickets, mg_result* results, int c
 int mg_server_stats(const mg_server* s, int* queued, int* running, size_t* resident_bytes);
 int mg_server_destroy(mg_server* s);
 
+/* ---- Solve without device allocation ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): mg_fmg_f64 (FMG from the FP64 right-hand
+ * sides rhs_dev[j-1] of levels j = 1..prm->L, as for mg_fmg_f64) on a
+ * hierarchy the library keeps in a static device array of MG_NOALLOC_BYTES
+ * per GPU (held until the process ends), then x_out_dev (dense
+ * (n_L + 2)^ndim doubles) = the finest iterate (exact for working widths
+ * up to 53 bits). Problems whose hierarchy needs more than MG_NOALLOC_BYTES
+ * (mg_hierarchy_bytes; 2D up to 513^2, 3D up to 65^3 fit) are rejected with
+ * BFP_ENOMEM. The first call for a parameter set on a device lays the
+ * hierarchy out in the array (host work and one synchronization of
+ * `stream`); later calls with the same parameters only enqueue the solve
+ * on `stream`. No hipMalloc / hipFree is called. Every call on a GPU uses
+ * that GPU's one array, which keeps the last call's contents: calls that
+ * overlap in time on one GPU (different streams or host threads without
+ * ordering) race and must be serialized by the caller.                   */
+#define MG_NOALLOC_BYTES (32u << 20)
+int mg_fmg_f64_noalloc(const mg_params* prm, const double* const* rhs_dev, double* x_out_dev,
+                       void* stream);
+
 /* ---- FP64 multigrid comparator ----
  * The same FMG schedule as the BFP solver (x_1 = 0, FMG prolongation, N
  * IR-V(nu1, nu2) iterations per level, relaxation y = c2 A r + c1 r, the

@@ -25,6 +25,7 @@ MG_DIAG_GAP_BINS = 61
 BFP_META_EXP, BFP_META_MAX, BFP_META_MIN, BFP_META_SAT, BFP_META_MU, BFP_META_FLAGS = range(6)
 MG_POLICY_Q, MG_POLICY_NN, MG_POLICY_NN_IR_FIRST_Q, MG_POLICY_NN_IR_FIRST2_Q, MG_POLICY_NN_IR_Q = range(5)
 MG_MAX_LEVELS = 16
+MG_NOALLOC_BYTES = 32 << 20
 
 
 class bfp_vec(C.Structure):
@@ -146,6 +147,7 @@ SIGNATURES = {
     "mg_server_stats": (I, [VP, P(I), P(I), P(C.c_size_t)]),
     "mg_server_collect": (I, [VP, P(C.c_uint64), P(mg_result), I, P(I)]),
     "mg_server_destroy": (I, [VP]),
+    "mg_fmg_f64_noalloc": (I, [P(mg_params), VP, VP, VP]),
     "mg_autotune": (I, [VP, I, VP, P(mg_tune_report)]),
     "fp64_mg_bytes": (C.c_size_t, [I, I]),
     "fp64_mg_create": (I, [I, I, I, I, I, C.c_double, C.c_double, VP, C.c_size_t, VP, P(VP)]),

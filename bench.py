@@ -77,6 +77,15 @@ def parse():
     return ap.parse_args()
 
 
+T0 = time.perf_counter()
+
+
+def progress(what: str) -> None:
+    """One progress line per finished leg on stderr (the JSON result is the
+    only line on stdout)."""
+    print(f"[bench {time.perf_counter() - T0:7.1f} s] {what}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -184,6 +193,7 @@ def main():
         err = math.sqrt(float(((u - us)[1:-1, 1:-1] ** 2).sum()) * h2)
         return err / disc
 
+    progress("dominant kernel timed")
     # ---------------------------------------------------------- main run --
     # per-level launch shapes of the star and transfer kernels, chosen by
     # the library's autotuner on this hierarchy (results do not depend on them)
@@ -216,9 +226,11 @@ def main():
     del H, x, b, r, xout
     torch.cuda.empty_cache()
 
+    progress("headline solve timed")
     # ------------------------------------- FP64 multigrid comparator ---
     fp64 = bench_fp64(P, torch, f, L, us, h2, disc, stream, ev)
 
+    progress("FP64 comparator timed")
     # --------------------------------------- plain stencil applies ------
     # z = A x (two int32 streams), 2D 4095^2 and 3D 511^3
     stencils = {}
@@ -257,14 +269,17 @@ def main():
         del x3, z3
         torch.cuda.empty_cache()
 
+    progress("stencil applies timed")
     # -------------------------------------------------- 33x33 latency ---
     c1 = bench_c1(P, W, torch, dev, stream, ev)
 
+    progress("33x33 latencies timed")
     # ------------------------------------------------------- 3D solve ---
     solve3d = None
     if args.level3d > 0:
         solve3d = bench_3d(args, P, W, torch, dev, stream, ev)
 
+    progress("3D solve done")
     # ------------------------------------------------------ width sweep ---
     # per finest inner width w (progressive: one bit less per coarser level):
     # the error with N = 2, then the smallest N <= 8 IR-V iterations per
@@ -302,6 +317,7 @@ def main():
     del Hn, xn
     torch.cuda.empty_cache()
 
+    progress("width sweep done")
     # ----------------------------------------- solve diagnostics -------
     diagnostics = estimation = None
     if not args.no_extras:
@@ -309,16 +325,19 @@ def main():
         diagnostics["ir_fallback"] = bench_fallback(P, W, torch, dev, stream, ev)
         estimation = bench_estimate(torch)
 
+    progress("diagnostics and estimation done")
     # --------------------------------------------------- batched solves ---
     batch = None
     if args.batch > 0:
         batch = bench_batch(args, P, W, np, torch, dev, stream, ev)
 
+    progress("batched leg done")
     # ---------------------------------------------------------- serving ---
     serving = None
     if args.serve > 0:
         serving = bench_serve(args, P, W, np, torch, dev)
 
+    progress("serving leg done")
     # ---------------------------------------------------- CPU baseline ----
     cpu = None
     if not args.no_cpu:
@@ -426,8 +445,10 @@ def bench_batch(args, P, W, np, torch, dev, stream, ev):
     calibrated number of IR-V iterations per level that reaches the
     discretization error (calibrate_n); every solve's error is checked."""
     solves = W.batch_trace(args.batch, seed=1)
-    sched = {L: calibrate_n(P, W, torch, dev, 2, L, 16)
-             for L in sorted({s.level for s in solves})}
+    sched = {}
+    for L in sorted({s.level for s in solves}):
+        sched[L] = calibrate_n(P, W, torch, dev, 2, L, 16)
+        progress(f"batched schedule level {L}: N = {sched[L][0]} (error {sched[L][1]:.3f}x)")
     prms = [P.batch_params(2, s.level, 16, N=sched[s.level][0] or 16) for s in solves]
     keep = {}
     table = torch.zeros(len(solves) * P.MG_MAX_LEVELS, dtype=torch.int64)
@@ -828,7 +849,11 @@ def bench_serve(args, P, W, np, torch, dev):
     trace = W.serving_trace(args.serve, rate=2000.0, seed=2)
     classes = sorted({(r.ndim, r.level, r.w) for r in trace})
     t0 = time.perf_counter()
-    sched = {c: calibrate_n(P, W, torch, dev, *c) for c in classes}
+    sched = {}
+    for c in classes:
+        sched[c] = calibrate_n(P, W, torch, dev, *c)
+        progress(f"serving schedule {c[0]}D level {c[1]} w {c[2]}: N = {sched[c][0]} "
+                 f"(error {sched[c][1]:.3f}x)")
     calib_s = time.perf_counter() - t0
     prms, rhs, outs, dofs = [], [], [], []
     for r in trace:

@@ -78,3 +78,28 @@ def test_batch_counters_and_errors():
     bad.ndim = 3
     with pytest.raises(P.BFPError):
         P.Batch([prms[0], bad])
+
+
+@pytest.mark.parametrize("w_inner", [8, 16])
+def test_batch_large_sides_match_solo(w_inner):
+    """Sides 129 and 257 (levels 7 and 8), which the batch runs entirely in
+    its one-workgroup-per-problem executor while a hierarchy of its own runs
+    them as launched kernels: every block of every level must agree."""
+    g = np.random.default_rng(77 + w_inner)
+    solves = [W.BatchSolve(int(s), W.draw_sine_modes(g, 2)) for s in (257, 129, 65, 257, 129)]
+    prms = [P.batch_params(2, s.level, w_inner) for s in solves]
+    B = P.Batch(prms)
+    keep, table = rhs_arrays(solves)
+    B.solve(table)
+    torch.cuda.synchronize()
+    at = 0
+    for i, s in enumerate(solves):
+        H = P.Hierarchy(prms[i])
+        for j in range(1, s.level + 1):
+            H.set_rhs(j, keep[at + j - 1])
+        at += s.level
+        H.fmg()
+        torch.cuda.synchronize()
+        for j in range(1, s.level + 1):
+            for which in (0, 1, 2):
+                assert same(B.get_vec(i, j, which), H.get_vec(j, which)), (i, s.side, j, which)

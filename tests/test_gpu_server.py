@@ -104,3 +104,17 @@ def test_graph_replays_match_eager_with_eager_work_between():
             # eager work between replays: a solve of another request
             assert torch.equal(alone(*items[(k + 1) % 3][:2]), refs[(k + 1) % 3])
             torch.cuda.synchronize()
+
+
+def test_server_large_requests_equal_solo():
+    """The request sizes of the serving trace's upper end (513^2, 1025^2,
+    65^3, 129^3), whose coarse levels the server runs in its executor up to
+    its larger point limit: each result equals the solve run alone."""
+    g = np.random.default_rng(31)
+    reqs = [(2, 513, 16), (2, 1025, 16), (3, 65, 16), (3, 129, 16), (2, 1025, 32), (3, 129, 8)]
+    reqs = [(nd, side, w, W.draw_sine_modes(g, nd)) for nd, side, w in reqs]
+    items = [make(r) for r in reqs]
+    S = P.Server(4 << 30, max_slots=3, exec_max_points=70000)
+    run_server(S, items)
+    for (prm, rhs, x), r in zip(items, reqs):
+        assert torch.equal(x, alone(prm, rhs)), r[:3]

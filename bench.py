@@ -71,13 +71,15 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: leave the environment's)")
-    ap.add_argument("--only", choices=["all", "kernel", "copy", "solve", "fp64", "coarse"],
+    ap.add_argument("--only", choices=["all", "kernel", "copy", "solve", "fp64", "coarse",
+                                       "tiles"],
                     default="all",
                     help="kernel: only the dominant-kernel loop (for profiler runs); copy: only "
                          "a plain 1 GiB device copy (counter calibration); solve: only --warmup + "
                          "--steps headline solves (autotuned shapes), nothing else; fp64: only "
                          "the FP64 comparator's solves; coarse: only FMG solves of the 65^2 grid "
-                         "(6 levels, all of them inside the coarse-level executor)")
+                         "(6 levels, all of them inside the coarse-level executor); tiles: only "
+                         "the tiled residual loop (T = 64, 4095^2)")
     return ap.parse_args()
 
 
@@ -145,6 +147,14 @@ def main():
         k1.record(stream)
         torch.cuda.synchronize()
         return k0.elapsed_time(k1) * 1000.0 / reps
+
+    if args.only == "tiles":
+        A, x, b, r, st = tiles_residual_setup(P, W, torch, dev, stream, L, 64)
+        one, mone = P.scalar(1, 0, 2), P.scalar(-1, 0, 1)
+        t = time_kernel(lambda: P.bfp_tiles_stencil_apply(A, x, one, mone, b, r, st, stream),
+                        args.kernel_reps)
+        print(json.dumps({"kernel": "tiled residual 4095^2 int32 T=64", "avg_us": t}))
+        return
 
     if args.only in ("solve", "fp64", "coarse"):
         # profiler runs: the headline solve (or the FP64 comparator, or a
@@ -306,6 +316,8 @@ def main():
         torch.cuda.empty_cache()
 
     progress("stencil applies timed")
+    tiles = bench_tiles(P, W, torch, dev, stream, time_kernel, L, args.kernel_reps)
+    progress("sub-maximal block sizes timed")
     # -------------------------------------------------- 33x33 latency ---
     c1 = bench_c1(P, W, torch, dev, stream, ev)
 
@@ -427,6 +439,7 @@ def main():
         "fp64_mg_comparator": fp64,
         "bfp_over_fp64_dof_per_s": round((dof / (ms * 1e-3)) / fp64["dof_per_s"], 2),
         "stencil_apply": stencils,
+        "sub_maximal_blocks": tiles,
         "solve_3d": solve3d,
         "c1_33x33": c1,
         "sweep": sweep,
@@ -472,6 +485,68 @@ def cpu_baseline(level, w, workers):
                       f"method on the {(1 << level) + 1}^2 grid ({level} levels, finest inner "
                       f"width {w}), exact Python integers; {wall:.1f} s wall, "
                       f"{min(secs):.1f}-{max(secs):.1f} s per solve; {cores} cores available"}
+
+
+def tiles_residual_setup(P, W, torch, dev, stream, L, T):
+    """x (manufactured solution plus noise) and b (f scaled as the solver's
+    b), both int32 tiles of T points, and the scaled 5-point operator."""
+    n = (1 << L) - 1
+    u = torch.from_numpy(W.manufactured_u(L, 2)).to(dev)
+    u[1:-1, 1:-1] += 1e-9 * torch.sin(torch.arange(n, device=dev, dtype=torch.float64) * 0.37)
+    fb = torch.from_numpy(W.manufactured_f(L, 2)).to(dev) * 2.0 ** (-2 * L - 2)
+    x, b, r = (P.Tiles(2, n, T, 32, 32) for _ in range(3))
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    P.bfp_tiles_from_f64(u, x, st, stream)
+    P.bfp_tiles_from_f64(fb, b, st, stream)
+    A = P.Stencil(2, P.BFP_STENCIL_A, -2, [0, -1, 0, -1, 4, -1, 0, -1, 0], 4)
+    return A, x, b, r, st
+
+
+def bench_tiles(P, W, torch, dev, stream, time_kernel, L, reps):
+    """Sub-maximal block sizes: the residual r = A x - b with one exponent
+    per tile of T row points (int32, 4095^2) for several T, against the
+    maximal block's residual; and the FP64 -> BFP quantization error by
+    block size (the paper's remark that the maximal block is the worst
+    case)."""
+    n = (1 << L) - 1
+    dof = n * n
+    out = {"residual_4095sq_int32": {}, "quantization_rel_l2_error": {}}
+    one, mone = P.scalar(1, 0, 2), P.scalar(-1, 0, 1)
+    for T in (1, 8, 64, 256):
+        A, x, b, r, st = tiles_residual_setup(P, W, torch, dev, stream, L, T)
+        t = time_kernel(lambda: P.bfp_tiles_stencil_apply(A, x, one, mone, b, r, st, stream), reps)
+        ntiles = n * -(-n // T)
+        nbytes = dof * 12.0 + 3 * 4.0 * ntiles
+        out["residual_4095sq_int32"][f"T{T}"] = {
+            "avg_us": round(t, 2), "bytes": nbytes, "gbs": round(nbytes / (t * 1e-6) / 1e9, 1),
+            "beyond_exact_range": int(st.item())}
+        del A, x, b, r, st
+    # the fields: the manufactured solution and a residual-like field of
+    # many scales (its FP64 residual after a perturbation)
+    u = torch.from_numpy(W.manufactured_u(L, 2)).to(dev)
+    g = torch.Generator(device=dev).manual_seed(5)
+    noise = torch.zeros_like(u)
+    noise[1:-1, 1:-1] = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64)
+    res = torch.zeros_like(u)
+    res[1:-1, 1:-1] = (4 * noise[1:-1, 1:-1] - noise[:-2, 1:-1] - noise[2:, 1:-1] -
+                       noise[1:-1, :-2] - noise[1:-1, 2:]) * torch.exp(
+        -20.0 * torch.linspace(0, 1, n, device=dev, dtype=torch.float64))[None, :]
+    for name, fld in (("solution", u), ("residual", res)):
+        ref = float(fld.norm())
+        row = {}
+        for w in (8, 12, 16):
+            v = P.Vec(2, n, w, P.storage_for(w))
+            P.bfp_vec_from_f64(fld, 0, v, stream)
+            errs = {"maximal": float((P.bfp_vec_to_f64(v) - fld).norm()) / ref}
+            for T in (256, 64, 8, 1):
+                t = P.Tiles(2, n, T, w, P.storage_for(w))
+                P.bfp_tiles_from_f64(fld, t, None, stream)
+                back = torch.zeros_like(fld)
+                P.bfp_tiles_to_f64(t, back, stream)
+                errs[f"T{T}"] = float((back - fld).norm()) / ref
+            row[f"w{w}"] = {k: float(f"{e:.3e}") for k, e in errs.items()}
+        out["quantization_rel_l2_error"][name] = row
+    return out
 
 
 def bench_batch(args, P, W, np, torch, dev, stream, ev):

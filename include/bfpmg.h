@@ -550,6 +550,70 @@ int fp64_mg_create(int ndim, int L, int nu1, int nu2, int N, double c1, double c
 int fp64_mg_fmg(fp64_mg* h, const double* const* rhs_dev, double* x_out_dev, void* stream);
 int fp64_mg_destroy(fp64_mg* h);
 
+/* ---- Sub-maximal block sizes (Section 2, Remark "Block size") ----
+ * A tiled BFP grid vector: the interior points of every grid row (fastest
+ * axis x) are split into tiles of T consecutive points (T a power of two in
+ * 1..256; the last tile of a row holds n mod T points when T does not
+ * divide n), and every tile is a BFP block of its own: one exponent and
+ * w-bit mantissas. Block size 1 is floating point with a w-bit significand
+ * rounded toward minus infinity; the rest of this library is the maximal
+ * block (one exponent per vector).
+ *   mant  device, the padded (n+2)^ndim grid (x fastest, row pitch `pitch`
+ *         elements from bfp_tiles_layout), int8/int16/int32 by
+ *         storage_bits; the ring is zero and no operation writes it.
+ *   exps  device, one int32 exponent per tile: n^(ndim-1) rows of ceil(n/T)
+ *         tiles, row r = (z-1) n + (y-1) in 3D and y - 1 in 2D (padded
+ *         coordinates), tile t holding x = t T + 1 .. min((t+1) T, n).
+ * Both arrays are caller-owned. Exponents must stay within +-2^30.
+ *
+ * Every operation computes each interior point's exact value and quantizes
+ * every output tile on its own to z->w bits with the normalized floor
+ * quantization of Section 2 (what Algorithm 1 returns, per tile): e = the
+ * largest nu over the tile's nonzero values minus w, m_i = floor(v_i / 2^e);
+ * an all-zero tile gets e = 1 - w. One pass, no reduction beyond a tile.
+ * Exact range: the terms of one point (for the stencil, alpha times a tap
+ * times a neighbour at exponent alpha.exp + A->exp + the neighbour's tile
+ * exponent, and beta y at beta.exp + y's tile exponent) are summed exactly
+ * while their exponents lie within 60 of each other; a point spread wider
+ * is set to zero and counted into *status_dev (device int32, added to, not
+ * reset; NULL: not counted). Coefficient limits: |alpha.m|, |beta.m| <
+ * 2^16, |taps| < 2^15 (else BFP_EWIDTH). Operands must share ndim, n and T
+ * (else BFP_ESHAPE). All calls are asynchronous on `stream`.             */
+typedef struct {
+  void* mant;
+  int32_t* exps;
+  int32_t w;            /* mantissa width, 1 <= w <= storage_bits            */
+  int32_t storage_bits; /* 8, 16 or 32                                       */
+  int32_t ndim;         /* 2 or 3                                            */
+  int32_t n;            /* interior points per dimension                     */
+  int32_t T;            /* tile size                                         */
+  int64_t pitch;        /* elements per row                                  */
+} bfp_tiles;
+/* Row pitch, mantissa bytes and exponent bytes of a tiled vector.        */
+int bfp_tiles_layout(int ndim, int n, int T, int storage_bits, int64_t* pitch, size_t* mant_bytes,
+                     size_t* exp_bytes);
+/* Zero mantissas (ring included) and every tile exponent 1 - w.          */
+int bfp_tiles_init(const bfp_tiles* t, void* stream);
+/* quant of FP64 data, tile by tile: x_dev is the padded (n+2)^ndim grid
+ * (contiguous, ring not read); non-finite values become 0 and are counted
+ * into *status_dev.                                                      */
+int bfp_tiles_from_f64(const double* x_dev, bfp_tiles* out, int32_t* status_dev, void* stream);
+/* m 2^e into the interior points of the padded (n+2)^ndim FP64 grid x_dev
+ * (ring untouched); exact while the values are normal or subnormal
+ * doubles.                                                               */
+int bfp_tiles_to_f64(const bfp_tiles* in, double* x_dev, void* stream);
+/* z = alpha A x + beta y (y may be NULL: z = alpha A x), A a same-grid star
+ * stencil (BFP_STENCIL_A with nonzero taps only at the centre and the 2 ndim
+ * axis neighbours; else BFP_EINVAL), the exact gemv row of Appendix B per
+ * point with the operand tiles' exponents. z must not alias x (y may).    */
+int bfp_tiles_stencil_apply(const bfp_stencil* A, const bfp_tiles* x, const bfp_scalar* alpha,
+                            const bfp_scalar* beta, const bfp_tiles* y, bfp_tiles* z,
+                            int32_t* status_dev, void* stream);
+/* z = alpha x + beta y point by point (the exact axpby row of Appendix B
+ * with each point's tile exponents); z may alias x or y.                 */
+int bfp_tiles_axpby(const bfp_scalar* alpha, const bfp_tiles* x, const bfp_scalar* beta,
+                    const bfp_tiles* y, bfp_tiles* z, int32_t* status_dev, void* stream);
+
 /* Launch-shape autotuning for the levels of h above its coarse-level
  * executor: per level j, every march length of the star kernel (rows or
  * planes per wave, 1..64) on the IR residual r = A x - b, and of the
@@ -583,6 +647,8 @@ int mg_autotune(mg_hierarchy* h, int reps, void* stream, mg_tune_report* out);
  * shapes mg_autotune chose; "exec_max_points" = largest grid (in interior points) whose
  * level runs inside the one-workgroup coarse-level programs a hierarchy
  * records at creation (0 = never; read by mg_hierarchy_bytes/create);
+ * "tiles2d_rows" = rows one wave of the 2D tiled stencil marches (tiles of
+ * at least 4 points; even values 2..1024, 0 = chosen from the grid size);
  * "diagnostics" = 1: hierarchies created while it is set keep the solve
  * diagnostics of mg_diag_read (0, the default: none, and no cost; read by
  * mg_hierarchy_bytes/create, which must see the same value).              */

@@ -134,6 +134,24 @@ def _combine(terms: list[tuple[int, int]]):
     return sum((Fraction(v) * Fraction(2) ** e for v, e in terms), Fraction(0))
 
 
+def star_point(A, n: int, p: tuple, xm, xe, alpha: Scalar, beta: Scalar | None = None,
+               ym=None, ye=None):
+    """Exact value of alpha A x (+ beta y) at interior point p, or None when
+    its terms spread beyond the exact range. xm(q), xe(q) give x's mantissa
+    and tile exponent at interior point q (ym, ye likewise for y)."""
+    terms = []
+    for o, t in A.taps.items():
+        if t == 0:
+            continue
+        q = tuple(pi + oi for pi, oi in zip(p, o))
+        if any(c < 1 or c > n for c in q):
+            continue   # ring: zero, no exponent
+        terms.append((alpha.m * t * int(xm(q)), alpha.e + A.e + int(xe(q))))
+    if ym is not None:
+        terms.append((beta.m * int(ym(p)), beta.e + int(ye(p))))
+    return _combine(terms)
+
+
 def stencil_apply(A, x: Tiled, alpha: Scalar, beta: Scalar | None, y: Tiled | None,
                   w_out: int) -> tuple[Tiled, int]:
     """z = alpha A x (+ beta y) on the interior, every output tile Q_w_out of
@@ -148,17 +166,9 @@ def stencil_apply(A, x: Tiled, alpha: Scalar, beta: Scalar | None, y: Tiled | No
     exact = np.zeros(x.m.shape, dtype=object)
     bad = 0
     for p in interior(d, n):
-        terms = []
-        for o, t in A.taps.items():
-            if t == 0:
-                continue
-            q = tuple(pi + oi for pi, oi in zip(p, o))
-            if any(c < 1 or c > n for c in q):
-                continue   # ring: zero, no exponent
-            terms.append((alpha.m * t * int(x.m[q]), alpha.e + A.e + x.tile_exp(q)))
-        if y is not None:
-            terms.append((beta.m * int(y.m[p]), beta.e + y.tile_exp(p)))
-        v = _combine(terms)
+        v = star_point(A, n, p, lambda q: x.m[q], x.tile_exp, alpha, beta,
+                       (lambda q: y.m[q]) if y is not None else None,
+                       y.tile_exp if y is not None else None)
         if v is None:
             bad += 1
             v = Fraction(0)

@@ -26,7 +26,8 @@ __all__ = [
     "bfp_normalize", "bfp_saturate_truncate", "bfp_cheby_coeffs", "BFPError",
     "BFP_NORMALIZE", "BFP_SATURATE", "BFP_STENCIL_A", "BFP_STENCIL_R", "BFP_STENCIL_P",
     "MG_POLICY_Q", "MG_POLICY_NN", "MG_POLICY_NN_IR_FIRST_Q", "MG_POLICY_NN_IR_FIRST2_Q",
-    "MG_POLICY_NN_IR_Q", "lib",
+    "MG_POLICY_NN_IR_Q", "lib", "Tiles", "bfp_tiles_from_f64", "bfp_tiles_to_f64",
+    "bfp_tiles_stencil_apply", "bfp_tiles_axpby",
 ]
 
 _DTYPES = {8: torch.int8, 16: torch.int16, 32: torch.int32}
@@ -269,6 +270,82 @@ def bfp_normalize(x: Vec, w_out: int, out: Vec, stream=None) -> None:
 def bfp_saturate_truncate(x: Vec, w_out: int, gamma, out: Vec, stream=None) -> None:
     check(lib.bfp_saturate_truncate(C.byref(x.c), w_out, _opt(gamma), C.byref(out.c),
                                     _stream(stream)), "bfp_saturate_truncate")
+
+
+# ------------------------------------------------ sub-maximal block sizes --
+
+class Tiles:
+    """A tiled BFP grid vector (bfp_tiles): padded row-pitched mantissas and
+    one int32 exponent per tile of T consecutive row points."""
+
+    def __init__(self, ndim: int, n: int, T: int, w: int, storage_bits: int | None = None,
+                 device: str | torch.device = "cuda", init: bool = True):
+        bits = storage_bits or storage_for(w)
+        pitch, mbytes, ebytes = C.c_int64(), C.c_size_t(), C.c_size_t()
+        check(lib.bfp_tiles_layout(ndim, n, T, bits, C.byref(pitch), C.byref(mbytes),
+                                   C.byref(ebytes)), "bfp_tiles_layout")
+        self.buf = torch.empty(mbytes.value, dtype=torch.uint8, device=device)
+        self.exps = torch.empty(ebytes.value // 4, dtype=torch.int32, device=device)
+        self.c = abi.bfp_tiles(self.buf.data_ptr(), self.exps.data_ptr(), w, bits, ndim, n, T,
+                               pitch.value)
+        if init:
+            check(lib.bfp_tiles_init(C.byref(self.c), _stream(None)), "bfp_tiles_init")
+
+    ndim = property(lambda self: self.c.ndim)
+    n = property(lambda self: self.c.n)
+    T = property(lambda self: self.c.T)
+    w = property(lambda self: self.c.w)
+    storage_bits = property(lambda self: self.c.storage_bits)
+
+    def mantissas(self) -> torch.Tensor:
+        """Device view of the (n+2)^ndim mantissas (ring included)."""
+        rows = (self.n + 2) ** (self.ndim - 1)
+        side = self.n + 2
+        raw = self.buf[:rows * self.c.pitch * self.storage_bits // 8]
+        return raw.view(_DTYPES[self.storage_bits]).view(rows, self.c.pitch)[:, :side].reshape(
+            (side,) * self.ndim)
+
+    def exponents(self) -> torch.Tensor:
+        """Device view of the tile exponents, (n^(ndim-1), ceil(n/T))."""
+        return self.exps.view(self.n ** (self.ndim - 1), -(-self.n // self.T))
+
+
+def bfp_tiles_from_f64(src: torch.Tensor, dst: Tiles, status: torch.Tensor | None = None,
+                       stream=None) -> None:
+    if src.dtype != torch.float64 or not src.is_cuda or not src.is_contiguous():
+        raise ValueError("src must be a contiguous float64 device tensor")
+    if src.numel() != (dst.n + 2) ** dst.ndim:
+        raise ValueError("src must hold (n+2)^ndim values")
+    check(lib.bfp_tiles_from_f64(_ptr(src), C.byref(dst.c), _opt_ptr(status), _stream(stream)),
+          "bfp_tiles_from_f64")
+
+
+def bfp_tiles_to_f64(src: Tiles, dst: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if dst is None:
+        dst = torch.zeros((src.n + 2,) * src.ndim, dtype=torch.float64, device="cuda")
+    if dst.dtype != torch.float64 or not dst.is_contiguous() or dst.numel() != (src.n + 2) ** src.ndim:
+        raise ValueError("dst must be a contiguous float64 tensor of (n+2)^ndim")
+    check(lib.bfp_tiles_to_f64(C.byref(src.c), _ptr(dst), _stream(stream)), "bfp_tiles_to_f64")
+    return dst
+
+
+def bfp_tiles_stencil_apply(A: Stencil, x: Tiles, alpha, beta, y: Tiles | None, z: Tiles,
+                            status: torch.Tensor | None = None, stream=None) -> None:
+    Ac = A.c()
+    check(lib.bfp_tiles_stencil_apply(C.byref(Ac), C.byref(x.c), _opt(alpha), _opt(beta),
+                                      C.byref(y.c) if y is not None else None, C.byref(z.c),
+                                      _opt_ptr(status), _stream(stream)),
+          "bfp_tiles_stencil_apply")
+
+
+def bfp_tiles_axpby(alpha, x: Tiles, beta, y: Tiles, z: Tiles, status: torch.Tensor | None = None,
+                    stream=None) -> None:
+    check(lib.bfp_tiles_axpby(_opt(alpha), C.byref(x.c), _opt(beta), C.byref(y.c), C.byref(z.c),
+                              _opt_ptr(status), _stream(stream)), "bfp_tiles_axpby")
+
+
+def _opt_ptr(t: torch.Tensor | None):
+    return _ptr(t) if t is not None else None
 
 
 def bfp_tuning_set(key: str, value: int) -> None:

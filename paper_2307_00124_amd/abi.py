@@ -43,6 +43,12 @@ class bfp_stencil(C.Structure):
                 ("w", C.c_int32), ("taps", C.c_int32 * 27)]
 
 
+class bfp_tiles(C.Structure):
+    _fields_ = [("mant", C.c_void_p), ("exps", C.c_void_p), ("w", C.c_int32),
+                ("storage_bits", C.c_int32), ("ndim", C.c_int32), ("n", C.c_int32),
+                ("T", C.c_int32), ("pitch", C.c_int64)]
+
+
 class bfp_gamma(C.Structure):
     _fields_ = [("rule", C.c_int32), ("a_meta", C.c_void_p), ("b_meta", C.c_void_p),
                 ("c", bfp_scalar)]
@@ -153,6 +159,14 @@ SIGNATURES = {
     "fp64_mg_create": (I, [I, I, I, I, I, C.c_double, C.c_double, VP, C.c_size_t, VP, P(VP)]),
     "fp64_mg_fmg": (I, [VP, VP, VP, VP]),
     "fp64_mg_destroy": (I, [VP]),
+    "bfp_tiles_layout": (I, [I, I, I, I, P(I64), P(C.c_size_t), P(C.c_size_t)]),
+    "bfp_tiles_init": (I, [P(bfp_tiles), VP]),
+    "bfp_tiles_from_f64": (I, [VP, P(bfp_tiles), VP, VP]),
+    "bfp_tiles_to_f64": (I, [P(bfp_tiles), VP, VP]),
+    "bfp_tiles_stencil_apply": (I, [P(bfp_stencil), P(bfp_tiles), P(bfp_scalar), P(bfp_scalar),
+                                    P(bfp_tiles), P(bfp_tiles), VP, VP]),
+    "bfp_tiles_axpby": (I, [P(bfp_scalar), P(bfp_tiles), P(bfp_scalar), P(bfp_tiles),
+                            P(bfp_tiles), VP, VP]),
     "bfp_tuning_set": (I, [C.c_char_p, I]),
     "bfp_tuning_get": (I, [C.c_char_p, C.POINTER(I)]),
     "bfp_last_error": (C.c_char_p, []),

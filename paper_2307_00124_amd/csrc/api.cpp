@@ -32,6 +32,12 @@ static int g_exec_max_points = 4096;
 
 int exec_max_points() { return g_exec_max_points; }
 
+// Rows one wave of the 2D tiled stencil kernel (tiles of >= 4 points)
+// marches (0: chosen from the grid size).
+static int g_tiles_rows = 0;
+
+int tiles_rows() { return g_tiles_rows; }
+
 // Hierarchies created while this is set keep solve diagnostics.
 static int g_diagnostics = 0;
 
@@ -651,6 +657,11 @@ int bfp_tuning_set(const char* key, int value) {
     return BFP_OK;
   }
   if (k == "star2d_small_n") { g_star2d_small_n = value; return BFP_OK; }
+  if (k == "tiles2d_rows") {
+    if (value > 1024) return fail(BFP_EINVAL, "tiles2d_rows is at most 1024");
+    g_tiles_rows = value;
+    return BFP_OK;
+  }
   if (value < 1) return fail(BFP_EINVAL, "value out of range");
   if (k == "star3d_rows") g_star3d_rows_large = value;
   else if (k == "star3d_small_n") g_star3d_small_n = value;
@@ -668,6 +679,7 @@ int bfp_tuning_get(const char* key, int* value) {
   else if (k == "star2d_small_n") *value = g_star2d_small_n;
   else if (k == "star3d_rows") *value = g_star3d_rows_large;
   else if (k == "star3d_small_n") *value = g_star3d_small_n;
+  else if (k == "tiles2d_rows") *value = g_tiles_rows;
   else return fail(BFP_EINVAL, "unknown tuning key %s", key);
   return BFP_OK;
 }

@@ -44,6 +44,8 @@ void set_slots(int64_t* slots);
 bool diagnostics_on();
 // grids of at most this many points run inside recorded programs (0: never)
 int exec_max_points();
+// rows per wave of the 2D tiled stencil kernel (tuning key "tiles2d_rows"; 0: automatic)
+int tiles_rows();
 // Give every op of a recorded program the slots of its metadata blocks in
 // the program's table of distinct blocks (filled into `metas`).
 int exec_assign_slots(std::vector<ExecOp>& ops, std::vector<int64_t*>& metas);

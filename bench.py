@@ -372,6 +372,36 @@ def main():
         diagnostics = bench_diag(P, torch, f, L, timed, stream)
         diagnostics["ir_fallback"] = bench_fallback(P, W, torch, dev, stream, ev)
         estimation = bench_estimate(torch)
+        # the headline solve on the schedule the estimation gives: check and
+        # inner widths from q_check / q_inner, eta from the V(1,0) scan; the
+        # smallest N per level that reaches the discretization error
+        from paper_2307_00124_amd import estimate as est
+        pe = est.apply_estimate(P.mg_params_init(2, L, args.w, True, 1, 0, 2,
+                                                 P.MG_POLICY_NN_IR_FIRST_Q,
+                                                 estimation["eta_v10"]["percent"]),
+                                estimation["q_check"], estimation["q_inner"])
+        pe.min_storage_bits = 32
+        est_solve = {"inner_widths": [pe.w_inner[j] for j in range(1, L + 1)],
+                     "check_widths": [pe.w_check[j] for j in range(1, L + 1)],
+                     "eta_percent": estimation["eta_v10"]["percent"]}
+        for N in range(2, 9):
+            pe.N = N
+            He = P.Hierarchy(pe)
+            xe = P.Vec(2, n, He.get_vec(L, 0).w, 32)
+            mse = timed(He, xe, 3, 1)
+            acce = accuracy(xe)
+            del He, xe
+            if N == 2:
+                est_solve.update({"ms_N2": round(mse, 3), "err_over_disc_N2": round(acce, 4)})
+            if acce <= 1.1:
+                est_solve.update({"N": N, "ms": round(mse, 3), "dof_per_s": dof / (mse * 1e-3),
+                                  "err_over_disc": round(acce, 4), "at_disc_error": True})
+                break
+        else:
+            est_solve.update({"N": "unreached up to 8", "err_over_disc_N8": round(acce, 4),
+                              "at_disc_error": False})
+        estimation["solve_4097sq"] = est_solve
+        torch.cuda.empty_cache()
 
     progress("diagnostics and estimation done")
     # --------------------------------------------------- batched solves ---

@@ -219,6 +219,23 @@ class Hierarchy:
         if self.policy not in POLICIES:
             raise ValueError(self.policy)
 
+    # The operator each call site uses. The finite-difference operators are
+    # exact at their minimal width, so quantizing them to a site's width
+    # (Algorithms IR, V and FMG quantize A, P and R on entry) changes
+    # nothing and one object serves every site; hierarchies whose operators
+    # are not exact (oracle.fe) return the site's quantized operator.
+    def op_A(self, l: int, site: str):
+        return self.A[l]
+
+    def op_R(self, l: int):
+        return self.R[l]
+
+    def op_P(self, l: int, site: str):
+        return self.P
+
+    def zero(self, l: int, w: int) -> BFP:
+        return zero_block(l, self.ndim, w)
+
 
 def rhs_block(f: np.ndarray, j: int, ndim: int, w: int) -> BFP:
     """b'_j = quant(f / s_j) at w bits: the exact FP64 samples of f scaled by
@@ -288,7 +305,7 @@ def relaxation(H: Hierarchy, l: int, r: BFP) -> BFP:
     """V relaxation y = c2 A r + c1 r (two Chebyshev steps from y = 0);
     gamma = c1 ||r||, since 0 <= D^-1 A <= 2I bounds ||y|| / ||r|| below c1."""
     s = H.smoother
-    return _quantize_op(H, "relax", blas.gemv(H.A[l], r, r, s.c2, s.c1),
+    return _quantize_op(H, "relax", blas.gemv(H.op_A(l, "relax"), r, r, s.c2, s.c1),
                         H.widths.inner[l], s.c1.value * r.norm_inf())
 
 
@@ -302,7 +319,7 @@ def v_residual(H: Hierarchy, l: int, y: BFP, r: BFP, gamma: Fraction) -> BFP:
     """V residual r_v = A y - r at the inner width (gamma from the caller:
     v_residual_gamma before the coarse correction, the latest residual of
     the cycle after it)."""
-    return _quantize_op(H, "v_res", blas.gemv(H.A[l], y, r, ONE, MINUS_ONE),
+    return _quantize_op(H, "v_res", blas.gemv(H.op_A(l, "v_res"), y, r, ONE, MINUS_ONE),
                         H.widths.inner[l], gamma)
 
 
@@ -310,14 +327,14 @@ def restriction(H: Hierarchy, l: int, rv: BFP) -> BFP:
     """Coarse residual R r_v on level l - 1; gamma = ||R|| ||r_v|| (triangle
     inequality). Its width is the inner width of level l, the recursion
     level of the call."""
-    return _quantize_op(H, "restrict", blas.spmv(H.R[l], rv), H.widths.inner[l],
-                        H.R[l].norm_inf() * rv.norm_inf())
+    return _quantize_op(H, "restrict", blas.spmv(H.op_R(l), rv), H.widths.inner[l],
+                        H.op_R(l).norm_inf() * rv.norm_inf())
 
 
 def v_correction(H: Hierarchy, l: int, y: BFP, d: BFP) -> BFP:
     """y - P d; gamma = ||y|| + ||d|| (nodal interpolation keeps
     ||P d|| = ||d||, then the triangle inequality)."""
-    return _quantize_op(H, "v_corr", blas.gemv(H.P, d, y, MINUS_ONE, ONE),
+    return _quantize_op(H, "v_corr", blas.gemv(H.op_P(l, "v_corr"), d, y, MINUS_ONE, ONE),
                         H.widths.inner[l], y.norm_inf() + d.norm_inf())
 
 
@@ -332,7 +349,7 @@ def ir_residual(H: Hierarchy, l: int, x: BFP, gamma: Fraction | None, first: boo
     """IR residual A x - b at the inner width; gamma is the norm of the
     previous residual (the assumption that the residual does not grow)."""
     r = _quantize_op(H, "ir_res_first" if first else "ir_res",
-                     blas.gemv(H.A[l], x, H.b[l], ONE, MINUS_ONE),
+                     blas.gemv(H.op_A(l, "ir_res"), x, H.b[l], ONE, MINUS_ONE),
                      H.widths.inner[l], gamma, force_q=force_q)
     H.ir_res_saturated = H.stats.last_saturated
     return r
@@ -348,7 +365,8 @@ def ir_correction(H: Hierarchy, l: int, x: BFP, y: BFP) -> BFP:
 def fmg_prolongation(H: Hierarchy, l: int, x: BFP) -> BFP:
     """P x_(l-1) at the working width of level l; gamma = ||x|| (nodal
     interpolation: ||P x|| = ||x||)."""
-    return _quantize_op(H, "fmg_prol", blas.spmv(H.P, x), H.widths.work[l], x.norm_inf())
+    return _quantize_op(H, "fmg_prol", blas.spmv(H.op_P(l, "fmg_prol"), x), H.widths.work[l],
+                        x.norm_inf())
 
 
 def _sweep(H: Hierarchy, l: int, y: BFP, r: BFP, gamma: Fraction) -> tuple[BFP, BFP]:
@@ -385,7 +403,7 @@ def ir_iteration(H: Hierarchy, l: int, x: BFP, gamma_res: Fraction | None,
 
 def fmg(H: Hierarchy, N: int) -> BFP:
     """FMG(nu1, nu2): coarse-to-fine with N IR-V iterations per level."""
-    x = zero_block(1, H.ndim, H.widths.work[1])
+    x = H.zero(1, H.widths.work[1])
     r_last = None
     for l in range(1, H.L + 1):
         if l > 1:

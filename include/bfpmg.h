@@ -614,6 +614,56 @@ int bfp_tiles_stencil_apply(const bfp_stencil* A, const bfp_tiles* x, const bfp_
 int bfp_tiles_axpby(const bfp_scalar* alpha, const bfp_tiles* x, const bfp_scalar* beta,
                     const bfp_tiles* y, bfp_tiles* z, int32_t* status_dev, void* stream);
 
+/* ---- The paper's finite-element model problems (Section 6) ----
+ * 1D Rayleigh-Ritz B-spline discretizations of Poisson (m = 1) and the
+ * biharmonic equation (m = 2) with strongly imposed Dirichlet conditions,
+ * solved by BFP FMG (Appendix C: FMG with N IR-V(1,0) iterations per
+ * level). The caller supplies the problem: per level j = 1..L the reference
+ * stiffness matrix K_hat_j (unit mesh spacing; K_j = h^(1-2m) K_hat_j), for
+ * j >= 2 the prolongation P_j from level j-1 (fine rows, coarse columns),
+ * both as banded matrices of exact rationals, and the FP64 load vector
+ * F_hat_j (F_j = h F_hat_j). The library applies Set-up S exactly
+ * (A_j = D_j^-1 K_j, b_j = D_j^-1 F_j, R_j = D_(j-1)^-1 P_j^T D_j, 128-bit
+ * rational arithmetic; BFP_EWIDTH if a value does not fit) and quantizes
+ * each operator per call site (A at w_check for the IR residual, A, R, P at
+ * w_inner inside the V-cycle, P at w_work for the FMG prolongation: Q_w of
+ * the whole matrix, one exponent). Chebyshev c1, c2 come from the
+ * Gershgorin bound of A on level min(5, L) and eta = eta_num / eta_den,
+ * floor-quantized to 16 bits. Every operation is a qcomp. Blocks are int32
+ * with 61-bit exact budgets: an operation whose terms could exceed them
+ * fails with BFP_EWIDTH (keep w_check + w_work and 16 + w_inner + the
+ * inner-width tap bits within 61). The hierarchy allocates its own device
+ * memory (hipMalloc at creation, freed by fe_hierarchy_destroy).        */
+typedef struct {
+  int32_t nrows, ncols;
+  int32_t band;            /* entries stored per row                        */
+  const int32_t* col0;     /* host: first column of each row                */
+  const int64_t* num;      /* host: nrows x band numerators                 */
+  const int64_t* den;      /* host: nrows x band denominators (> 0)         */
+} fe_rational_band;
+typedef struct {
+  int32_t m;               /* 1: Poisson, 2: biharmonic                     */
+  int32_t L, N;            /* levels; IR-V iterations per FMG level         */
+  int32_t eta_num, eta_den;
+  int32_t w_check[MG_MAX_LEVELS + 1], w_work[MG_MAX_LEVELS + 1],
+      w_inner[MG_MAX_LEVELS + 1];
+} fe_params;
+typedef struct fe_hierarchy fe_hierarchy;
+/* K[j-1], P[j-1] (P[0] unused), F[j-1]: level j. Synchronizes.           */
+int fe_hierarchy_create(const fe_params* prm, const fe_rational_band* K, const fe_rational_band* P,
+                        const double* const* F, void* stream, fe_hierarchy** out);
+/* FMG from x_1 = 0; the solution is block x of level L. Asynchronous.     */
+int fe_fmg(fe_hierarchy* h, void* stream);
+/* Copy block `which` (0 x, 1 b, 2 the last IR residual) of a level to the
+ * host: n + 2 int32 mantissas (the two ends zero) into mant_host (may be
+ * NULL), its exponent, its n. Synchronizes the device.                    */
+int fe_get(fe_hierarchy* h, int level, int which, int32_t* mant_host, int64_t* exp_out, int* n_out);
+/* The quantized Chebyshev coefficients the hierarchy uses.               */
+int fe_coefficients(const fe_hierarchy* h, bfp_scalar* c1, bfp_scalar* c2);
+/* Bytes the operations moved and kernel launches, since creation.         */
+int fe_counters(const fe_hierarchy* h, double* bytes, int64_t* launches);
+int fe_hierarchy_destroy(fe_hierarchy* h);
+
 /* Launch-shape autotuning for the levels of h above its coarse-level
  * executor: per level j, every march length of the star kernel (rows or
  * planes per wave, 1..64) on the IR residual r = A x - b, and of the

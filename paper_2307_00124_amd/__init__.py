@@ -348,6 +348,80 @@ def _opt_ptr(t: torch.Tensor | None):
     return _ptr(t) if t is not None else None
 
 
+# ------------------------------------ finite-element model problems --
+
+class FEHierarchy:
+    """fe_hierarchy: the 1D B-spline FE model problems of Section 6 in BFP
+    FMG. K, P: per level, banded matrices of Fractions (objects with nrows,
+    ncols, col0, vals as workloads.fe.Band; P[0] unused); F: per level, the
+    FP64 load vectors (host arrays); widths: dicts level -> width."""
+
+    def __init__(self, m: int, L: int, N: int, K: list, P: list, F: list, w_check: dict,
+                 w_work: dict, w_inner: dict, eta=(23, 100), stream=None):
+        import numpy as np
+        prm = abi.fe_params()
+        prm.m, prm.L, prm.N = m, L, N
+        prm.eta_num, prm.eta_den = eta
+        for j in range(1, L + 1):
+            prm.w_check[j], prm.w_work[j], prm.w_inner[j] = w_check[j], w_work[j], w_inner[j]
+        self._keep = []
+
+        def band(B):
+            width = max(len(r) for r in B.vals)
+            width = min(width, B.ncols)
+            col0 = np.zeros(B.nrows, dtype=np.int32)
+            num = np.zeros((B.nrows, width), dtype=np.int64)
+            den = np.ones((B.nrows, width), dtype=np.int64)
+            for i, row in enumerate(B.vals):
+                c = max(0, min(B.col0[i], B.ncols - width))
+                col0[i] = c
+                for t, v in enumerate(row):
+                    at = B.col0[i] + t - c
+                    if v != 0:
+                        num[i, at], den[i, at] = v.numerator, v.denominator
+            self._keep += [col0, num, den]
+            return abi.fe_rational_band(B.nrows, B.ncols, width, col0.ctypes.data,
+                                        num.ctypes.data, den.ctypes.data)
+        Ks = (abi.fe_rational_band * L)(*[band(K[j]) for j in range(L)])
+        Ps = (abi.fe_rational_band * L)(*([abi.fe_rational_band()] +
+                                           [band(P[j]) for j in range(1, L)]))
+        Fs = [np.ascontiguousarray(f, dtype=np.float64) for f in F]
+        self._keep += Fs
+        Fp = (C.c_void_p * L)(*[f.ctypes.data for f in Fs])
+        h = C.c_void_p()
+        check(lib.fe_hierarchy_create(C.byref(prm), Ks, Ps, Fp, _stream(stream), C.byref(h)),
+              "fe_hierarchy_create")
+        self.h = h
+        self.L = L
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.fe_hierarchy_destroy(self.h)
+            self.h = None
+
+    def fmg(self, stream=None) -> None:
+        check(lib.fe_fmg(self.h, _stream(stream)), "fe_fmg")
+
+    def get(self, level: int, which: int = 0):
+        """(mantissas with the two zero ends, exponent) of a block."""
+        import numpy as np
+        e, n = C.c_int64(), C.c_int()
+        check(lib.fe_get(self.h, level, which, None, C.byref(e), C.byref(n)), "fe_get")
+        out = np.zeros(n.value + 2, dtype=np.int32)
+        check(lib.fe_get(self.h, level, which, out.ctypes.data, C.byref(e), C.byref(n)), "fe_get")
+        return out, e.value
+
+    def coefficients(self):
+        c1, c2 = abi.bfp_scalar(), abi.bfp_scalar()
+        check(lib.fe_coefficients(self.h, C.byref(c1), C.byref(c2)), "fe_coefficients")
+        return (c1.m, c1.exp), (c2.m, c2.exp)
+
+    def counters(self):
+        b, n = C.c_double(), C.c_int64()
+        check(lib.fe_counters(self.h, C.byref(b), C.byref(n)), "fe_counters")
+        return b.value, n.value
+
+
 def bfp_tuning_set(key: str, value: int) -> None:
     check(lib.bfp_tuning_set(key.encode(), int(value)), "bfp_tuning_set")
 

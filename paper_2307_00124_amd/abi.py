@@ -49,6 +49,17 @@ class bfp_tiles(C.Structure):
                 ("T", C.c_int32), ("pitch", C.c_int64)]
 
 
+class fe_rational_band(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("band", C.c_int32),
+                ("col0", C.c_void_p), ("num", C.c_void_p), ("den", C.c_void_p)]
+
+
+class fe_params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("L", C.c_int32), ("N", C.c_int32), ("eta_num", C.c_int32),
+                ("eta_den", C.c_int32), ("w_check", C.c_int32 * 17), ("w_work", C.c_int32 * 17),
+                ("w_inner", C.c_int32 * 17)]
+
+
 class bfp_gamma(C.Structure):
     _fields_ = [("rule", C.c_int32), ("a_meta", C.c_void_p), ("b_meta", C.c_void_p),
                 ("c", bfp_scalar)]
@@ -167,6 +178,12 @@ SIGNATURES = {
                                     P(bfp_tiles), P(bfp_tiles), VP, VP]),
     "bfp_tiles_axpby": (I, [P(bfp_scalar), P(bfp_tiles), P(bfp_scalar), P(bfp_tiles),
                             P(bfp_tiles), VP, VP]),
+    "fe_hierarchy_create": (I, [P(fe_params), VP, VP, VP, VP, P(VP)]),
+    "fe_fmg": (I, [VP, VP]),
+    "fe_get": (I, [VP, I, I, VP, P(I64), P(I)]),
+    "fe_coefficients": (I, [VP, P(bfp_scalar), P(bfp_scalar)]),
+    "fe_counters": (I, [VP, P(C.c_double), P(I64)]),
+    "fe_hierarchy_destroy": (I, [VP]),
     "bfp_tuning_set": (I, [C.c_char_p, I]),
     "bfp_tuning_get": (I, [C.c_char_p, C.POINTER(I)]),
     "bfp_last_error": (C.c_char_p, []),

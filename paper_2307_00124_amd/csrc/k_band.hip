@@ -1,0 +1,58 @@
+// Banded BFP matrix-vector products on 1D blocks (the finite-element model
+// problems): z = Q(alpha M x + beta y) with M a BFP matrix of one exponent
+// whose row i holds `band` integer taps from input column col0[i] (the exact
+// gemv / spmv rows of Appendix B), through the common epilogue. Vectors are
+// padded 1D blocks (index 0 and n + 1 are the zero ends); an identity
+// matrix (no taps) gives the pointwise axpby / sub rows.
+#include "band.hpp"
+#include "epilogue.hpp"
+
+namespace bfpk {
+
+template <int PASS, bool HASY, bool IDENT>
+__global__ __launch_bounds__(kBlock) void k_band(const BandLaunch L) {
+  const int32_t* X = L.x;
+  const int32_t* Y = L.y;
+  Epi<PASS, HASY> E;
+  E.init(L.op);
+  with_fast(E, [&](auto fast_tag) {
+    constexpr int VAR = decltype(fast_tag)::value;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < L.nout;
+         i += (int64_t)gridDim.x * kBlock) {
+      int64_t g = 0;
+      if (IDENT) {
+        g = X[1 + i];
+      } else {
+        const int32_t* t = L.taps + i * L.band;
+        const int32_t* xr = X + 1 + L.col0[i];
+        for (int k = 0; k < L.band; ++k) g += (int64_t)t[k] * xr[k];
+      }
+      const int32_t yv = HASY ? Y[1 + i] : 0;
+      const int64_t out = E.template put<VAR>(g, yv, true);
+      if (PASS != kQ1) L.z[1 + i] = (int32_t)out;
+    }
+  });
+  E.finish();
+}
+
+template <int PASS, bool HASY, bool IDENT>
+static hipError_t band_go(const BandLaunch& L, hipStream_t s) {
+  const int64_t blocks = (L.nout + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_band<PASS, HASY, IDENT>),
+                     dim3((unsigned)(blocks < kMaxBlocks ? (blocks > 0 ? blocks : 1) : kMaxBlocks)),
+                     dim3(kBlock), 0, s, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_band(const BandLaunch& L, hipStream_t s) {
+  const bool q1 = L.op.mode == kModeQ1;
+  const bool id = L.taps == nullptr;
+  if (L.op.has_y) {
+    if (id) return q1 ? band_go<kQ1, true, true>(L, s) : band_go<kOut, true, true>(L, s);
+    return q1 ? band_go<kQ1, true, false>(L, s) : band_go<kOut, true, false>(L, s);
+  }
+  if (id) return q1 ? band_go<kQ1, false, true>(L, s) : band_go<kOut, false, true>(L, s);
+  return q1 ? band_go<kQ1, false, false>(L, s) : band_go<kOut, false, false>(L, s);
+}
+
+}  // namespace bfpk

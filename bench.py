@@ -318,6 +318,7 @@ def main():
     progress("stencil applies timed")
     tiles = bench_tiles(P, W, torch, dev, stream, time_kernel, L, args.kernel_reps)
     progress("sub-maximal block sizes timed")
+    fe_rows = bench_fe(P, np, torch, stream, ev)
     # -------------------------------------------------- 33x33 latency ---
     c1 = bench_c1(P, W, torch, dev, stream, ev)
 
@@ -470,6 +471,7 @@ def main():
         "bfp_over_fp64_dof_per_s": round((dof / (ms * 1e-3)) / fp64["dof_per_s"], 2),
         "stencil_apply": stencils,
         "sub_maximal_blocks": tiles,
+        "finite_elements": fe_rows,
         "solve_3d": solve3d,
         "c1_33x33": c1,
         "sweep": sweep,
@@ -576,6 +578,69 @@ def bench_tiles(P, W, torch, dev, stream, time_kernel, L, reps):
                 errs[f"T{T}"] = float((back - fld).norm()) / ref
             row[f"w{w}"] = {k: float(f"{e:.3e}") for k, e in errs.items()}
         out["quantization_rel_l2_error"][name] = row
+    return out
+
+
+def fe_widths(kind, p, L):
+    """The widest schedule the library's 61-bit exact budgets allow for the
+    finite-element problems: A and b at 28 bits, x at 28, the V-cycle at 20
+    (the paper's widths for these problems grow past 32 bits on fine
+    levels, so the levels below are chosen where these suffice)."""
+    return ({j: 28 for j in range(1, L + 1)}, {j: 28 for j in range(1, L + 1)},
+            {j: 20 for j in range(1, L + 1)})
+
+
+def bench_fe(P, np, torch, stream, ev):
+    """The paper's finite-element model problems (Section 6): BFP FMG on 1D
+    B-spline discretizations, the error against the exact discrete solution
+    (FP64 with exactly computed residuals), the smallest N up to 8 that
+    reaches 1.1x the discretization error (the paper's N first), time per
+    solve (HIP events), launches and DoF/s."""
+    from workloads import fe as FW
+    out = []
+    for kind, p, L in (("poisson", 1, 12), ("poisson", 2, 5), ("poisson", 3, 4),
+                       ("biharmonic", 3, 6), ("biharmonic", 5, 3), ("biharmonic", 6, 3)):
+        m = 1 if kind == "poisson" else 2
+        ck, wk, inn = fe_widths(kind, p, L)
+        K = [FW.stiffness(j, p, m) for j in range(1, L + 1)]
+        Pm = [None] + [FW.prolongation(j, p, m) for j in range(2, L + 1)]
+        F = [FW.load_vector(kind, j, p) for j in range(1, L + 1)]
+        disc = FW.l2_error(kind, p, L, FW.discrete_solution(kind, p, L))
+        paper_N = FW.PAPER_N[(kind, p)]
+        row = {"problem": kind, "p": p, "L": L, "dof": FW.n_unknowns(L, p, m), "paper_N": paper_N,
+               "widths": [ck[L], wk[L], inn[L]]}
+        tried = [paper_N] + [n for n in range(1, 9) if n != paper_N]
+        for N in tried:
+            G = P.FEHierarchy(m, L, N, K, Pm, F, ck, wk, inn)
+            for _ in range(2):
+                G.fmg(stream)
+            torch.cuda.synchronize()
+            b0, l0 = G.counters()
+            e0, e1 = ev(), ev()
+            e0.record()
+            reps = 10
+            for _ in range(reps):
+                G.fmg(stream)
+            e1.record()
+            torch.cuda.synchronize()
+            b1, l1 = G.counters()
+            ms = e0.elapsed_time(e1) / reps
+            mant, e = G.get(L, 0)
+            ratio = FW.l2_error(kind, p, L, mant[1:-1].astype(np.float64) * 2.0 ** e) / disc
+            if N == paper_N:
+                row.update({"err_over_disc_paper_N": round(ratio, 4), "ms_paper_N": round(ms, 3)})
+            if ratio <= 1.1:
+                row.update({"N": N, "ms": round(ms, 3), "err_over_disc": round(ratio, 4),
+                            "launches": int((l1 - l0) / reps), "at_disc_error": True,
+                            "dof_per_s": row["dof"] / (ms * 1e-3)})
+                break
+            del G
+        else:
+            row.update({"N": "unreached up to 8", "err_over_disc_N8": round(ratio, 4),
+                        "at_disc_error": False})
+        row["discretization_error_l2"] = disc
+        progress(f"finite elements {kind} p {p} L {L}: N = {row['N']}")
+        out.append(row)
     return out
 
 

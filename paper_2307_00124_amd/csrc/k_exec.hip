@@ -64,19 +64,39 @@ __device__ __forceinline__ void stv(void* p, int bits, int64_t i, int64_t v) {
 
 typedef int64_t MetaRow[kExMetaF];
 
+// What an op leaves to publish once the program loop's barrier has passed:
+// the workgroup reduction of its outputs (every wave reduces the per-wave
+// partials itself and writes the same metadata into the LDS mirror, so no
+// wave waits for another's serial tail), or a zero fill's metadata. Kept
+// in registers, uniformly, by every wave.
+constexpr int kFinNone = 0, kFinOut = 1, kFinZero = 2;
+struct Fin {
+  MetaRow* z;
+  int kind;
+  int par;          // which half of the double-buffered partials
+  int64_t eo;       // output exponent
+  int64_t* diag;    // diagnostics of the op (DG programs only)
+  int dbin, dsat;
+};
+
 // Operand metadata read from the LDS mirror by slot.
 struct PendingDiag;
 struct LdsMeta {
   MetaRow* lm;
   PendingDiag* pend;   // where the op leaves its diagnostic counts
+  Fin* fin;            // the op's pending publication
+  int32_t* red;        // per-wave partials: [2][3][waves] outputs, then [waves] mu
   int s[5];
   __device__ __forceinline__ int64_t operator()(int k, int f) const { return lm[s[k]][f]; }
 };
 
-__device__ __forceinline__ LdsMeta lds_meta(MetaRow* lm, PendingDiag* pend, const int16_t* slot) {
+__device__ __forceinline__ LdsMeta lds_meta(MetaRow* lm, PendingDiag* pend, Fin* fin,
+                                            int32_t* red, const int16_t* slot) {
   LdsMeta m;
   m.lm = lm;
   m.pend = pend;
+  m.fin = fin;
+  m.red = red;
   m.s[kOpX] = slot[0];
   m.s[kOpY] = slot[1] >= 0 ? slot[1] : slot[0];
   m.s[kOpZ] = slot[2];
@@ -85,13 +105,15 @@ __device__ __forceinline__ LdsMeta lds_meta(MetaRow* lm, PendingDiag* pend, cons
   return m;
 }
 
-// Workgroup reductions: per-wave partials (DPP) in LDS, then wave 0
-// reduces them and lane 0 publishes the result in the output's LDS row.
-template <int NT>
-struct Red {
-  static constexpr int kWaves = NT / 64;
-  int32_t v[3][kWaves];
-};
+// After one lane (or a few) of a wave wrote metadata rows that every lane
+// reads next: the wave's LDS accesses execute in order, so only the
+// compiler must be kept from moving the other lanes' reads above the
+// writes (which it may do without a fence: no write is on their path).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // An op's diagnostic counts, left by its reduction for thread 0 to issue
 // at the start of the next op (then nothing on the op's own path waits for
@@ -102,46 +124,71 @@ struct PendingDiag {
   int64_t nsat;
 };
 
+// Workgroup reductions: per-wave partials (DPP) in LDS, then every wave
+// reduces the partials itself. The first qcomp pass needs mu* at once (one
+// barrier, then each wave writes the same mu* into the output's row); an
+// output pass only leaves its partials, published after the program loop's
+// barrier (the one that also makes the op's stores visible), so an op
+// costs one barrier per pass.
 template <int NT, int PASS, bool HASY, bool DG>
-__device__ __forceinline__ void ex_finish(const Epi<PASS, HASY, DG>& E, MetaRow& zm,
-                                          PendingDiag& pend) {
-  constexpr int kExWaves = NT / 64;
-  __shared__ Red<NT> R;
-  auto& red = R.v;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+__device__ __forceinline__ void ex_finish(const Epi<PASS, HASY, DG>& E, const LdsMeta& ma) {
+  constexpr int kW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  MetaRow& zm = ma.lm[ma.s[kOpZ]];
   if (PASS == kQ1) {
+    int32_t* r = ma.red + 6 * kW;
     const int32_t m = wave_max32((int32_t)E.tmu);
-    if (lane == 0) red[0][wave] = m;
+    if (lane == 0) r[wave] = m;
     __syncthreads();
-    if (wave == 0) {
-      const int32_t b = wave_max32(lane < kExWaves ? red[0][lane] : 1);
-      if (lane == 0) zm[kMetaMu] = b;
-    }
+    int32_t b = 1;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) b = r[k] > b ? r[k] : b;
+    if (lane == 0) zm[kMetaMu] = b;
+    wave_sync_lds();
   } else {
+    Fin& f = *ma.fin;
+    int32_t* r = ma.red + f.par * 3 * kW;
     const int32_t a = wave_max32(E.tmax), b = wave_min32(E.tmin), c = wave_sum32(E.tsat);
     if (lane == 0) {
-      red[0][wave] = a;
-      red[1][wave] = b;
-      red[2][wave] = c;
+      r[wave] = a;
+      r[kW + wave] = b;
+      r[2 * kW + wave] = c;
     }
-    __syncthreads();
-    if (wave == 0) {
-      const bool in = lane < kExWaves;
-      const int32_t mx = wave_max32(in ? red[0][lane] : 0);
-      const int32_t mn = wave_min32(in ? red[1][lane] : 0);
-      const int32_t st = wave_sum32(in ? red[2][lane] : 0);
-      if (lane == 0) {
-        zm[kMetaMax] = mx;
-        zm[kMetaMin] = mn;
-        zm[kMetaSat] = st;
-        zm[kMetaExp] = E.R.eo;
-        if (DG && E.diag) pend = PendingDiag{E.diag, E.dbin, E.dsat, st};
-      }
-    }
+    f.z = &zm;
+    f.kind = kFinOut;
+    f.eo = E.R.eo;
+    f.diag = DG ? E.diag : nullptr;
+    f.dbin = E.dbin;
+    f.dsat = E.dsat;
   }
-  // the second qcomp pass reads mu* at once; after an output pass the
-  // program loop's barrier follows (red[] is next written after it)
-  if (PASS == kQ1) __syncthreads();
+}
+
+// Publish the previous op's metadata (after the program loop's barrier).
+template <int NT, bool DG>
+__device__ __forceinline__ void ex_publish(Fin& f, const int32_t* red, PendingDiag& pend) {
+  constexpr int kW = NT / 64;
+  const int lane = threadIdx.x & 63;
+  if (f.kind == kFinOut) {
+    const int32_t* r = red + f.par * 3 * kW;
+    int32_t mx = 0, mn = 0, st = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+      mx = r[k] > mx ? r[k] : mx;
+      mn = r[kW + k] < mn ? r[kW + k] : mn;
+      st += r[2 * kW + k];
+    }
+    if (lane == 0) {
+      (*f.z)[kMetaMax] = mx;
+      (*f.z)[kMetaMin] = mn;
+      (*f.z)[kMetaSat] = st;
+      (*f.z)[kMetaExp] = f.eo;
+    }
+    if (DG && threadIdx.x == 0 && f.diag) pend = PendingDiag{f.diag, f.dbin, f.dsat, st};
+  } else if (f.kind == kFinZero) {
+    if (lane < kExMetaF) (*f.z)[lane] = lane == kMetaExp ? f.eo : (lane == kMetaMu ? 1 : 0);
+  }
+  wave_sync_lds();
+  f.kind = kFinNone;
 }
 
 // Visit every interior point (z, y, x) of an n^ND output grid: the exact
@@ -185,8 +232,15 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
     int64_t g[U], zo[U];
     int32_t yv[U];
     bool ok[U];
+    // rounds holding a point of this wave (the rest are skipped uniformly)
+    const int w0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      ok[u] = false;
+      g[u] = 0;
+      zo[u] = 0;
+      yv[u] = 0;
+      if (w0 + u * NT >= tot) continue;
       const int i = threadIdx.x + u * NT;
       int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
       ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
@@ -201,21 +255,23 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
       yv[u] = HASY ? ldx(ys, row * py + x) : 0;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) E1.template put<kVarGen>(g[u], yv[u], ok[u]);
-    ex_finish<NT>(E1, ma.lm[ma.s[kOpZ]], *ma.pend);   // mu*, then a barrier
+    for (int u = 0; u < U; ++u)
+      if (w0 + u * NT < tot) E1.template put<kVarGen>(g[u], yv[u], ok[u]);
+    ex_finish<NT>(E1, ma);   // mu*, after one barrier
     Epi<kOut, HASY, DG> E2;
     E2.init(q2, ma);
     auto store = [&](auto var_tag) {
       constexpr int VAR = decltype(var_tag)::value;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        if (w0 + u * NT >= tot) continue;
         const int64_t v = E2.template put<VAR>(g[u], yv[u], ok[u]);
         if (ok[u]) stv(zp, zbits, zo[u], v);
       }
     };
     if (E2.fast) store(std::integral_constant<int, kVarFast>());
     else store(std::integral_constant<int, kVarGen>());
-    ex_finish<NT>(E2, ma.lm[ma.s[kOpZ]], *ma.pend);
+    ex_finish<NT>(E2, ma);
     return;
   } else {
   Epi<PASS, HASY, DG> E;
@@ -229,12 +285,19 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   const int64_t side = n + 2;
   auto body = [&](auto var_tag) {
     constexpr int VAR = decltype(var_tag)::value;
-    for (int i0 = threadIdx.x; i0 < tot; i0 += U * NT) {
+    const int w0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63;
+    for (int r0 = 0; w0 + r0 < tot; r0 += U * NT) {
+      const int i0 = threadIdx.x + r0;
       int64_t g[U], zo[U];
       int32_t yv[U];
       bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        ok[u] = false;
+        g[u] = 0;
+        zo[u] = 0;
+        yv[u] = 0;
+        if (w0 + r0 + u * NT >= tot) continue;
         const int i = i0 + u * NT;
         int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
         ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
@@ -250,6 +313,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        if (w0 + r0 + u * NT >= tot) continue;
         const int64_t v = E.template put<VAR>(g[u], yv[u], ok[u]);
         if (PASS != kQ1 && ok[u]) stv(zp, zbits, zo[u], v);
       }
@@ -258,7 +322,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   // the fast epilogue when no intermediate can overflow (decided once per op)
   if (PASS != kQ1 && E.fast) body(std::integral_constant<int, kVarFast>());
   else body(std::integral_constant<int, kVarGen>());
-  ex_finish<NT>(E, ma.lm[ma.s[kOpZ]], *ma.pend);
+  ex_finish<NT>(E, ma);
   }
 }
 
@@ -368,20 +432,22 @@ __device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op,
   });
 }
 
+// (the metadata is published after the loop's barrier, like an op's)
 template <int NT>
-__device__ __forceinline__ void ex_zero(const ZeroOp& Z, int64_t* zm, uintptr_t base) {
+__device__ __forceinline__ void ex_zero(const ZeroOp& Z, MetaRow* zm, Fin& fin, uintptr_t base) {
   uint4* p = static_cast<uint4*>(rel(Z.mant, base));
   const int64_t n16 = Z.bytes / 16;
   for (int64_t i = threadIdx.x; i < n16; i += NT) p[i] = make_uint4(0, 0, 0, 0);
-  if (threadIdx.x < kExMetaF)
-    zm[threadIdx.x] = threadIdx.x == kMetaExp ? Z.exp : (threadIdx.x == kMetaMu ? 1 : 0);
+  fin.z = zm;
+  fin.kind = kFinZero;
+  fin.eo = Z.exp;
 }
 
 
 template <int NT, int ND, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, PendingDiag* pend,
-                                            int mode, uintptr_t base) {
-  const LdsMeta ma = lds_meta(lm, pend, op.slot);
+                                            Fin* fin, int32_t* red, int mode, uintptr_t base) {
+  const LdsMeta ma = lds_meta(lm, pend, fin, red, op.slot);
   if (op.kind == kExStar) {
     ex_star<NT, ND, PASS, HASY, DG>(op.u.star, with_mode(op.u.star.op, mode), ma, base);
   } else if (op.kind == kExPoint) {
@@ -500,6 +566,10 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
   __shared__ MetaRow lm[kExecMaxMeta];
   __shared__ ExecOp buf[2];
   __shared__ PendingDiag pend;
+  __shared__ int32_t red[7 * (NT / 64)];
+  Fin fin;
+  fin.kind = kFinNone;
+  fin.par = 0;
   const int t = threadIdx.x;
   if (DG && t == 0) pend.diag = nullptr;
   const uint32_t* gw = reinterpret_cast<const uint32_t*>(ops);
@@ -517,8 +587,9 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
       diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);
       pend.diag = nullptr;
     }
+    fin.par = k & 1;
     if (op.kind == kExZero) {
-      ex_zero<NT>(op.u.zero, lm[op.slot[2]], base);
+      ex_zero<NT>(op.u.zero, &lm[op.slot[2]], fin, base);
     } else if (op.kind == kExConv) {
       ex_conv<NT, ND>(op.u.conv, lm[op.slot[2]], base, rhs);
     } else {
@@ -526,17 +597,19 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
                                           : (op.kind == kExPoint ? op.u.pt.op.has_y
                                                                  : op.u.tr.op.has_y);
       if (op.mode == kExModeQ) {
-        if (hasy) ex_dispatch<NT, ND, kQF, true, DG>(op, lm, &pend, kModeQ2, base);
-        else ex_dispatch<NT, ND, kQF, false, DG>(op, lm, &pend, kModeQ2, base);
+        if (hasy) ex_dispatch<NT, ND, kQF, true, DG>(op, lm, &pend, &fin, red, kModeQ2, base);
+        else ex_dispatch<NT, ND, kQF, false, DG>(op, lm, &pend, &fin, red, kModeQ2, base);
       } else if (hasy) {
-        ex_dispatch<NT, ND, kOut, true, DG>(op, lm, &pend, op.mode, base);
+        ex_dispatch<NT, ND, kOut, true, DG>(op, lm, &pend, &fin, red, op.mode, base);
       } else {
-        ex_dispatch<NT, ND, kOut, false, DG>(op, lm, &pend, op.mode, base);
+        ex_dispatch<NT, ND, kOut, false, DG>(op, lm, &pend, &fin, red, op.mode, base);
       }
     }
     if (pre) bw[((k + 1) & 1) * kOpWords + t] = nextw;
     __syncthreads();
+    ex_publish<NT, DG>(fin, red, pend);
   }
+  __syncthreads();
   for (int i = t; i < nmeta * kExMetaF; i += NT)
     ((BFP_GLOBAL int64_t*)rel(metas[i / kExMetaF], base))[i % kExMetaF] = lm[i / kExMetaF][i % kExMetaF];
   if (DG && t == 0 && pend.diag) diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);

@@ -48,16 +48,20 @@ __device__ __forceinline__ Src src_of(const void* p, int bits, uintptr_t base) {
   return Src{(const BFP_GLOBAL char*)rel(p, base), bits == 32 ? 2 : (bits == 16 ? 1 : 0), bits};
 }
 
-// element i, sign-extended from its storage width
+// element i, sign-extended from its storage width (W32: every operand of
+// the op is stored in 32 bits, a plain load)
+template <bool W32>
 __device__ __forceinline__ int32_t ldx(const Src& s, int64_t i) {
+  if (W32) return ((const BFP_GLOBAL int32_t*)s.p)[i];
   const int64_t off = i << s.sh;
   const uint32_t word = *(const BFP_GLOBAL uint32_t*)(s.p + (off & ~(int64_t)3));
   const int at = (int)(off & 3) * 8;
   return (int32_t)(word << (32 - s.bits - at)) >> (32 - s.bits);
 }
 
+template <bool W32>
 __device__ __forceinline__ void stv(void* p, int bits, int64_t i, int64_t v) {
-  if (bits == 32) ((BFP_GLOBAL int32_t*)p)[i] = (int32_t)v;
+  if (W32 || bits == 32) ((BFP_GLOBAL int32_t*)p)[i] = (int32_t)v;
   else if (bits == 16) ((BFP_GLOBAL int16_t*)p)[i] = (int16_t)v;
   else ((BFP_GLOBAL int8_t*)p)[i] = (int8_t)v;
 }
@@ -209,7 +213,7 @@ __device__ __forceinline__ OpArgs with_mode(const OpArgs& a, int mode) {
 // otherwise the two passes run one after the other.
 constexpr int kQF = 3;
 
-template <int NT, int ND, int PASS, bool HASY, bool DG, int U, typename Gather>
+template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32, int U, typename Gather>
 __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uintptr_t base,
                                         int n, const void* yp, int ybits, int64_t py, void* zp0,
                                         int zbits, int64_t pz, Gather&& gather) {
@@ -219,8 +223,8 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
     const int tot = ND == 3 ? 1 << (3 * lg) : 1 << (2 * lg);
     const OpArgs q1 = with_mode(op, kModeQ1), q2 = with_mode(op, kModeQ2);
     if (tot > U * NT) {
-      ex_loop<NT, ND, kQ1, HASY, DG, U>(q1, ma, base, n, yp, ybits, py, zp0, zbits, pz, gather);
-      ex_loop<NT, ND, kOut, HASY, DG, U>(q2, ma, base, n, yp, ybits, py, zp0, zbits, pz, gather);
+      ex_loop<NT, ND, kQ1, HASY, DG, W32, U>(q1, ma, base, n, yp, ybits, py, zp0, zbits, pz, gather);
+      ex_loop<NT, ND, kOut, HASY, DG, W32, U>(q2, ma, base, n, yp, ybits, py, zp0, zbits, pz, gather);
       return;
     }
     const int M = (1 << lg) - 1;
@@ -252,7 +256,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
       const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
       g[u] = gather(z, y, x);
       zo[u] = row * pz + x;
-      yv[u] = HASY ? ldx(ys, row * py + x) : 0;
+      yv[u] = HASY ? ldx<W32>(ys, row * py + x) : 0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -266,7 +270,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
       for (int u = 0; u < U; ++u) {
         if (w0 + u * NT >= tot) continue;
         const int64_t v = E2.template put<VAR>(g[u], yv[u], ok[u]);
-        if (ok[u]) stv(zp, zbits, zo[u], v);
+        if (ok[u]) stv<W32>(zp, zbits, zo[u], v);
       }
     };
     if (E2.fast) store(std::integral_constant<int, kVarFast>());
@@ -309,13 +313,13 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
         const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
         g[u] = gather(z, y, x);
         zo[u] = row * pz + x;
-        yv[u] = HASY ? ldx(ys, row * py + x) : 0;
+        yv[u] = HASY ? ldx<W32>(ys, row * py + x) : 0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (w0 + r0 + u * NT >= tot) continue;
         const int64_t v = E.template put<VAR>(g[u], yv[u], ok[u]);
-        if (PASS != kQ1 && ok[u]) stv(zp, zbits, zo[u], v);
+        if (PASS != kQ1 && ok[u]) stv<W32>(zp, zbits, zo[u], v);
       }
     }
   };
@@ -326,7 +330,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   }
 }
 
-template <int NT, int ND, int PASS, bool HASY, bool DG>
+template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32>
 __device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
@@ -335,13 +339,13 @@ __device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, c
   int32_t t[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, DG, 4>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, 4>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t b = (ND == 3 ? (int64_t)z * side + y : (int64_t)y) * px + x;
-    int64_t g = (int64_t)t[0] * ldx(xs, b) + (int64_t)t[1] * ldx(xs, b - 1) +
-                (int64_t)t[2] * ldx(xs, b + 1) + (int64_t)t[3] * ldx(xs, b - px) +
-                (int64_t)t[4] * ldx(xs, b + px);
-    if (ND == 3) g += (int64_t)t[5] * ldx(xs, b - zs) + (int64_t)t[6] * ldx(xs, b + zs);
+    int64_t g = (int64_t)t[0] * ldx<W32>(xs, b) + (int64_t)t[1] * ldx<W32>(xs, b - 1) +
+                (int64_t)t[2] * ldx<W32>(xs, b + 1) + (int64_t)t[3] * ldx<W32>(xs, b - px) +
+                (int64_t)t[4] * ldx<W32>(xs, b + px);
+    if (ND == 3) g += (int64_t)t[5] * ldx<W32>(xs, b - zs) + (int64_t)t[6] * ldx<W32>(xs, b + zs);
     return g;
   });
 }
@@ -352,7 +356,7 @@ __device__ __forceinline__ constexpr int tidx(int iz, int iy, int ix) {
 }
 
 // restriction: z[I] = sum_o t[o] x[2I + o] over the 3^ND offsets
-template <int NT, int ND, int PASS, bool HASY, bool DG>
+template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32>
 __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
@@ -360,7 +364,7 @@ __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArg
   int32_t t[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, DG, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
                                                L.py, L.z, L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
     int64_t g = 0;
 #pragma unroll
@@ -370,7 +374,7 @@ __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArg
         const int64_t row = ND == 3 ? (int64_t)(2 * z + oz) * sf + (2 * y + oy) : (int64_t)(2 * y + oy);
 #pragma unroll
         for (int ox = -1; ox <= 1; ++ox)
-          g += (int64_t)t[tidx<ND>(oz + 1, oy + 1, ox + 1)] * ldx(xs, row * px + 2 * x + ox);
+          g += (int64_t)t[tidx<ND>(oz + 1, oy + 1, ox + 1)] * ldx<W32>(xs, row * px + 2 * x + ox);
       }
     return g;
   });
@@ -381,7 +385,7 @@ __device__ __forceinline__ void ex_restrict(const TransferLaunch& L, const OpArg
 // where along an even dimension only e = 0 contributes (offset 0) and along
 // an odd one e selects the offset 2e - 1. The tap of each corner is chosen
 // from the parities with selects, so the loads stay branch-free.
-template <int NT, int ND, int PASS, bool HASY, bool DG>
+template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32>
 __device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
@@ -389,7 +393,7 @@ __device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs
   int32_t t[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, DG, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, ND == 3 ? 1 : 2>(op, ma, base, (int)L.n_out, L.y, L.ybits,
                                                L.py, L.z, L.zbits, L.pz, [&](int z, int y, int x) -> int64_t {
     const int qz = z & 1, qy = y & 1, qx = x & 1;
     const int jz = z >> 1, jy = y >> 1, jx = x >> 1;
@@ -414,21 +418,21 @@ __device__ __forceinline__ void ex_prolong(const TransferLaunch& L, const OpArgs
                 tap = match ? cand : tap;
               }
           const int64_t row = ND == 3 ? (int64_t)(jz + ez) * sc + (jy + ey) : (int64_t)(jy + ey);
-          g += (int64_t)tap * ldx(xs, row * px + jx + ex);
+          g += (int64_t)tap * ldx<W32>(xs, row * px + jx + ex);
         }
     return g;
   });
 }
 
-template <int NT, int ND, int PASS, bool HASY, bool DG>
+template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32>
 __device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
   const int64_t px = L.px, side = L.n + 2;
-  ex_loop<NT, ND, PASS, HASY, DG, 4>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, 4>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
-    return ldx(xs, row * px + x);
+    return ldx<W32>(xs, row * px + x);
   });
 }
 
@@ -444,18 +448,18 @@ __device__ __forceinline__ void ex_zero(const ZeroOp& Z, MetaRow* zm, Fin& fin, 
 }
 
 
-template <int NT, int ND, int PASS, bool HASY, bool DG>
+template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32>
 __device__ __forceinline__ void ex_dispatch(const ExecOp& op, MetaRow* lm, PendingDiag* pend,
                                             Fin* fin, int32_t* red, int mode, uintptr_t base) {
   const LdsMeta ma = lds_meta(lm, pend, fin, red, op.slot);
   if (op.kind == kExStar) {
-    ex_star<NT, ND, PASS, HASY, DG>(op.u.star, with_mode(op.u.star.op, mode), ma, base);
+    ex_star<NT, ND, PASS, HASY, DG, W32>(op.u.star, with_mode(op.u.star.op, mode), ma, base);
   } else if (op.kind == kExPoint) {
-    ex_point<NT, ND, PASS, HASY, DG>(op.u.pt, with_mode(op.u.pt.op, mode), ma, base);
+    ex_point<NT, ND, PASS, HASY, DG, W32>(op.u.pt, with_mode(op.u.pt.op, mode), ma, base);
   } else {
     const OpArgs a = with_mode(op.u.tr.op, mode);
-    if (op.u.tr.kind == 1) ex_restrict<NT, ND, PASS, HASY, DG>(op.u.tr, a, ma, base);
-    else ex_prolong<NT, ND, PASS, HASY, DG>(op.u.tr, a, ma, base);
+    if (op.u.tr.kind == 1) ex_restrict<NT, ND, PASS, HASY, DG, W32>(op.u.tr, a, ma, base);
+    else ex_prolong<NT, ND, PASS, HASY, DG, W32>(op.u.tr, a, ma, base);
   }
 }
 
@@ -529,7 +533,7 @@ __device__ __forceinline__ void ex_conv(const ConvOp& C, MetaRow& zm, uintptr_t 
     }
     tmax = (int32_t)v > tmax ? (int32_t)v : tmax;
     tmin = (int32_t)v < tmin ? (int32_t)v : tmin;
-    stv(mant, C.bits, row * C.pitch + x, v);
+    stv<false>(mant, C.bits, row * C.pitch + x, v);
   }
   tmax = wave_max32(tmax);
   tmin = wave_min32(tmin);
@@ -558,8 +562,10 @@ constexpr int kOpWords = (int)(sizeof(ExecOp) / 4);
 static_assert(sizeof(ExecOp) % 4 == 0 && kOpWords <= kBatchThreads, "ExecOp copy layout");
 
 // Run one program (ops[0..count), metadata table metas[0..nmeta)) with this
-// workgroup; pointers are relocated by `base`.
-template <int NT, int ND, bool DG>
+// workgroup; pointers are relocated by `base`. SPEC32: ops whose operands
+// are all stored in 32 bits take plain loads and stores (a second copy of
+// the op code, kept to the single-hierarchy programs without diagnostics).
+template <int NT, int ND, bool DG, bool SPEC32>
 __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int count,
                                             int64_t* const* __restrict__ metas, int nmeta,
                                             uintptr_t base, const double* const* rhs) {
@@ -596,13 +602,30 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
       const int hasy = op.kind == kExStar ? op.u.star.op.has_y
                                           : (op.kind == kExPoint ? op.u.pt.op.has_y
                                                                  : op.u.tr.op.has_y);
-      if (op.mode == kExModeQ) {
-        if (hasy) ex_dispatch<NT, ND, kQF, true, DG>(op, lm, &pend, &fin, red, kModeQ2, base);
-        else ex_dispatch<NT, ND, kQF, false, DG>(op, lm, &pend, &fin, red, kModeQ2, base);
-      } else if (hasy) {
-        ex_dispatch<NT, ND, kOut, true, DG>(op, lm, &pend, &fin, red, op.mode, base);
+      auto run_op = [&](auto w32_tag) {
+        constexpr bool W32 = decltype(w32_tag)::value;
+        if (op.mode == kExModeQ) {
+          if (hasy) ex_dispatch<NT, ND, kQF, true, DG, W32>(op, lm, &pend, &fin, red, kModeQ2, base);
+          else ex_dispatch<NT, ND, kQF, false, DG, W32>(op, lm, &pend, &fin, red, kModeQ2, base);
+        } else if (hasy) {
+          ex_dispatch<NT, ND, kOut, true, DG, W32>(op, lm, &pend, &fin, red, op.mode, base);
+        } else {
+          ex_dispatch<NT, ND, kOut, false, DG, W32>(op, lm, &pend, &fin, red, op.mode, base);
+        }
+      };
+      if constexpr (SPEC32) {
+        int xb, yb, zb;
+        if (op.kind == kExStar) {
+          xb = op.u.star.xbits; yb = op.u.star.ybits; zb = op.u.star.zbits;
+        } else if (op.kind == kExPoint) {
+          xb = op.u.pt.xbits; yb = op.u.pt.ybits; zb = op.u.pt.zbits;
+        } else {
+          xb = op.u.tr.xbits; yb = op.u.tr.ybits; zb = op.u.tr.zbits;
+        }
+        if (xb == 32 && zb == 32 && (!hasy || yb == 32)) run_op(std::true_type());
+        else run_op(std::false_type());
       } else {
-        ex_dispatch<NT, ND, kOut, false, DG>(op, lm, &pend, &fin, red, op.mode, base);
+        run_op(std::false_type());
       }
     }
     if (pre) bw[((k + 1) & 1) * kOpWords + t] = nextw;
@@ -624,7 +647,7 @@ __global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict_
   // the program runner's first barrier)
   __shared__ const double* srhs[kMaxLevels];
   if (threadIdx.x < kMaxLevels) srhs[threadIdx.x] = rhs.p[threadIdx.x];
-  run_program<kExecThreads, ND, DG>(ops, count, metas, nmeta, 0, srhs);
+  run_program<kExecThreads, ND, DG, !DG>(ops, count, metas, nmeta, 0, srhs);
 }
 
 template <int ND>
@@ -632,7 +655,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_exec_batch(
     const BatchEntry* __restrict__ entries, const ExecOp* __restrict__ ops,
     int64_t* const* __restrict__ metas, const double* const* __restrict__ rhs_table) {
   const BatchEntry& E = entries[blockIdx.x];
-  run_program<kBatchThreads, ND, false>(ops + E.op_begin, E.op_count, metas + E.meta_begin,
+  run_program<kBatchThreads, ND, false, false>(ops + E.op_begin, E.op_count, metas + E.meta_begin,
                                         E.nmeta, E.base, rhs_table + (int64_t)E.prob * kMaxLevels);
 }
 

@@ -169,7 +169,9 @@ def main():
             run = lambda: Hc.fmg(stream)
         elif args.only == "solve":
             H = make(args.w)
-            H.autotune(reps=10, stream=stream)
+            for j in range(1, L + 1):
+                H.set_rhs(j, f[j], stream)
+            H.autotune_solve(reps=3, stream=stream)
             run = lambda: H.fmg_f64(rhs, stream)
         else:
             F = P.FP64MG(P.mg_params_init(2, L, 32, True, 1, 0, 2, P.MG_POLICY_NN_IR_FIRST_Q, 23))
@@ -242,8 +244,9 @@ def main():
     progress("dominant kernel timed")
     # ---------------------------------------------------------- main run --
     # per-level launch shapes of the star and transfer kernels, chosen by
-    # the library's autotuner on this hierarchy (results do not depend on them)
-    tune = H.autotune(reps=10, stream=stream) if not args.no_autotune else None
+    # the library's autotuner from the time of whole solves on this
+    # hierarchy (results do not depend on them)
+    tune = H.autotune_solve(reps=3, stream=stream) if not args.no_autotune else None
     xout = P.Vec(2, n, H.get_vec(L, 0).w, 32)
     ms = timed(H, xout, args.steps, args.warmup)
     ratio = accuracy(xout)

@@ -541,6 +541,17 @@ class Hierarchy:
         kernels, timed on this hierarchy (overwrites its work blocks)."""
         r = abi.mg_tune_report()
         check(lib.mg_autotune(self.h, reps, _stream(stream), C.byref(r)), "mg_autotune")
+        return self._tune_dict(r)
+
+    def autotune_solve(self, reps: int = 3, stream=None) -> dict:
+        """mg_autotune_solve: the same shapes chosen by the time of whole FMG
+        solves on this hierarchy's right-hand sides (times in us per solve)."""
+        r = abi.mg_tune_report()
+        check(lib.mg_autotune_solve(self.h, reps, _stream(stream), C.byref(r)), "mg_autotune_solve")
+        return self._tune_dict(r)
+
+    @staticmethod
+    def _tune_dict(r) -> dict:
         out = {}
         for j in range(r.first_level, r.last_level + 1):
             out[j] = {"star_rows": r.star_rows[j] or "default",

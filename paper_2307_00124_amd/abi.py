@@ -166,6 +166,7 @@ SIGNATURES = {
     "mg_server_destroy": (I, [VP]),
     "mg_fmg_f64_noalloc": (I, [P(mg_params), VP, VP, VP]),
     "mg_autotune": (I, [VP, I, VP, P(mg_tune_report)]),
+    "mg_autotune_solve": (I, [VP, I, VP, P(mg_tune_report)]),
     "fp64_mg_bytes": (C.c_size_t, [I, I]),
     "fp64_mg_create": (I, [I, I, I, I, I, C.c_double, C.c_double, VP, C.c_size_t, VP, P(VP)]),
     "fp64_mg_fmg": (I, [VP, VP, VP, VP]),

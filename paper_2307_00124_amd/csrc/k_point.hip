@@ -29,27 +29,33 @@ __global__ __launch_bounds__(kBlock) void k_point(const PointLaunch L) {
   const TX* X = static_cast<const TX*>(L.x);
   const TY* Y = static_cast<const TY*>(L.y);
   TZ* Z = static_cast<TZ*>(L.z);
-  Epi<PASS, HASY> E;
-  E.init(L.op);
   // kPU items per round, their loads issued before any of them is used (a
   // round keeps kPU times the bytes of one item in flight)
   constexpr int kPU = 4;
+  int32_t xv[kPU][4], yv[kPU][4];
+  int64_t rr[kPU], c[kPU];
+  bool live[kPU];
+  auto fetch = [&](int64_t it0) {
+#pragma unroll
+    for (int u = 0; u < kPU; ++u) {
+      const int64_t it = it0 + (int64_t)u * gridDim.x;
+      rr[u] = interior_row((it < items ? it : 0) / nchunk, n, L.ndim);
+      c[u] = ((it < items ? it : 0) % nchunk) * 1024 + threadIdx.x * 4;
+      live[u] = it < items && c[u] < n + 2;
+      ld4(X, rr[u] * L.px + c[u], xv[u], live[u]);
+      if (HASY) ld4(Y, rr[u] * L.py + c[u], yv[u], live[u]);
+      else yv[u][0] = yv[u][1] = yv[u][2] = yv[u][3] = 0;
+    }
+  };
+  // the first round's loads are issued before the epilogue reads the
+  // operands' metadata (they do not depend on it), so the round trips overlap
+  fetch(blockIdx.x);
+  Epi<PASS, HASY> E;
+  E.init(L.op);
   with_fast(E, [&](auto fast_tag) {
     constexpr int VAR = decltype(fast_tag)::value;
     for (int64_t it0 = blockIdx.x; it0 < items; it0 += (int64_t)kPU * gridDim.x) {
-      int32_t xv[kPU][4], yv[kPU][4];
-      int64_t rr[kPU], c[kPU];
-      bool live[kPU];
-#pragma unroll
-      for (int u = 0; u < kPU; ++u) {
-        const int64_t it = it0 + (int64_t)u * gridDim.x;
-        rr[u] = interior_row((it < items ? it : 0) / nchunk, n, L.ndim);
-        c[u] = ((it < items ? it : 0) % nchunk) * 1024 + threadIdx.x * 4;
-        live[u] = it < items && c[u] < n + 2;
-        ld4(X, rr[u] * L.px + c[u], xv[u], live[u]);
-        if (HASY) ld4(Y, rr[u] * L.py + c[u], yv[u], live[u]);
-        else yv[u][0] = yv[u][1] = yv[u][2] = yv[u][3] = 0;
-      }
+      if (it0 != blockIdx.x) fetch(it0);
 #pragma unroll
       for (int u = 0; u < kPU; ++u) {
         if (!live[u]) continue;

@@ -1096,6 +1096,76 @@ int mg_autotune(mg_hierarchy* h, int reps, void* stream, mg_tune_report* out) {
   return rc;
 }
 
+// Launch shapes chosen by the time of whole FMG solves: each level's star
+// and transfer march lengths in turn (coordinate descent from the finest
+// level down, the other levels at their current shapes), so every shape is
+// judged in the conditions of the solve (caches, the executor's tails, the
+// neighbouring launches) rather than by back-to-back launches of one op.
+int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* out) {
+  if (!h) return fail(BFP_EINVAL, "NULL hierarchy");
+  if (reps < 1 || reps > 100) return fail(BFP_EINVAL, "reps must be in 1..100");
+  hipStream_t s = (hipStream_t)stream;
+  const int nd = h->prm.ndim, L = h->prm.L;
+  const double b0 = h->bytes;
+  const int64_t l0 = h->launches;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_check(hipEventCreate(&e0), "event");
+  if (!rc) rc = hip_check(hipEventCreate(&e1), "event");
+  mg_tune_report rep;
+  std::memset(&rep, 0, sizeof rep);
+  rep.first_level = h->Lc + 1;
+  rep.last_level = L;
+  // time of one FMG solve: median of three runs of `reps` solves
+  auto timed = [&](float* us) {
+    float t[3];
+    for (int k = 0; k < 3 && !rc; ++k) {
+      rc = mg_fmg(h, s);
+      if (!rc) rc = hip_check(hipEventRecord(e0, s), "event record");
+      for (int i = 0; i < reps && !rc; ++i) rc = mg_fmg(h, s);
+      if (!rc) rc = hip_check(hipEventRecord(e1, s), "event record");
+      if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
+      float ms = 0;
+      if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+      t[k] = ms * 1000.0f / reps;
+    }
+    if (rc) return;
+    std::sort(t, t + 3);
+    *us = t[1];
+  };
+  const int cands[] = {1, 2, 4, 8, 16, 32, 64};
+  // one kind (0 star, 1 transfer) on level j: keep the fastest shape
+  auto search = [&](int kind, int j, int maxc, int32_t* pick_out, float* best_out,
+                    float* default_out) {
+    set_level_rows(kind, nd, j, 0);
+    float best = 0, t = 0;
+    timed(&best);
+    *default_out = best;
+    int pick = 0;
+    for (int c : cands) {
+      if (rc || c > maxc) break;
+      set_level_rows(kind, nd, j, c);
+      timed(&t);
+      if (!rc && t < best * 0.998f) { best = t; pick = c; }
+    }
+    if (rc) return;
+    set_level_rows(kind, nd, j, pick);
+    *pick_out = pick;
+    *best_out = best;
+  };
+  for (int j = L; j > h->Lc && !rc; --j) {
+    search(0, j, h->lv[j].n, &rep.star_rows[j], &rep.star_us[j], &rep.star_default_us[j]);
+    if (!rc && j >= 2)
+      search(1, j, std::min<int64_t>(32, h->lv[j - 1].n + 1), &rep.transfer_rows[j],
+             &rep.transfer_us[j], &rep.transfer_default_us[j]);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->bytes = b0;
+  h->launches = l0;
+  if (!rc && out) *out = rep;
+  return rc;
+}
+
 int mg_diag_read(mg_hierarchy* h, int64_t* host_out, int reset, void* stream) {
   if (!h || !host_out) return fail(BFP_EINVAL, "NULL argument");
   if (!h->diag)

@@ -78,20 +78,24 @@ __global__ __launch_bounds__(kBlock) void k_star2d(const StarLaunch L) {
   TZ* Z = static_cast<TZ*>(L.z);
   const int32_t t0 = L.taps[0], txm = L.taps[1], txp = L.taps[2], tym = L.taps[3],
                 typ = L.taps[4];
+  // the first batch's loads are issued before the epilogue reads the
+  // operands' metadata (they do not depend on it), so the two round trips
+  // overlap
+  const bool live = r0 < r1;
+  int32_t win[U + 2][4];                   // lines r-1 .. r+U of the current batch
+  int32_t yv[U][4], eg[U];
+  ld4(X, (r0 - 1) * px + c, win[0], act && live);
+  ld4(X, r0 * px + c, win[1], act && live);
+  star2d_fetch<TX, TY, U, HASY, YX>(X, Y, r0, n, px, py, c, lane, act && live, act_y && live,
+                                    *reinterpret_cast<int32_t(*)[U][4]>(&win[2]), yv, eg);
   Epi<PASS, HASY> E;
   E.init(L.op);
   bool colok[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) colok[q] = c + q >= 1 && c + q <= n;
-  if (r0 < r1) with_fast(E, [&](auto fast_tag) {
+  if (live) with_fast(E, [&](auto fast_tag) {
     constexpr int VAR = decltype(fast_tag)::value;
-    int32_t win[U + 2][4];                 // lines r-1 .. r+U of the current batch
-    int32_t yv[U][4], eg[U];
     int32_t nx[U][4], ny[U][4], ne[U];     // the next batch in flight
-    ld4(X, (r0 - 1) * px + c, win[0], act);
-    ld4(X, r0 * px + c, win[1], act);
-    star2d_fetch<TX, TY, U, HASY, YX>(X, Y, r0, n, px, py, c, lane, act, act_y,
-                                  *reinterpret_cast<int32_t(*)[U][4]>(&win[2]), yv, eg);
     for (int64_t r = r0; r < r1; r += U) {
       star2d_fetch<TX, TY, U, HASY, YX>(X, Y, r + U, n, px, py, c, lane, act, act_y, nx, ny, ne);
 #pragma unroll

@@ -106,9 +106,24 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const TransferLaunch L) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) colok[q] = c + q >= 1 && c + q <= nf;
   const bool act_y = c < py, act_z = c < pz;
+  const bool live = b0 < b1 && (ND == 2 || jy3 <= nc);
+  // 2D: the first two coarse lines (and y rows) are loaded before the
+  // epilogue reads the operands' metadata, so the two round trips overlap
+  int32_t A2[3], B2[3], y0[4], y1[4];
+  if (ND == 2) {
+    pro_load(X, b0 * px, cc, px, live, lane, A2);
+    pro_load(X, (b0 + 1) * px, cc, px, live && b0 + 1 <= nc + 1, lane, B2);
+    if (HASY) {
+      ld4(Y, (2 * b0) * py + c, y0, live && act_y && 2 * b0 <= nf);
+      ld4(Y, (2 * b0 + 1) * py + c, y1, live && act_y && 2 * b0 + 1 <= nf);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y0[q] = y1[q] = 0;
+    }
+  }
   Epi<PASS, HASY> E;
   E.init(L.op);
-  if (b0 < b1 && (ND == 2 || jy3 <= nc)) with_fast(E, [&](auto fast_tag) {
+  if (live) with_fast(E, [&](auto fast_tag) {
     constexpr int VAR = decltype(fast_tag)::value;
     // fine line (plane fz, row fy) from the coarse lines held in A (line
     // index b) and B (line b + 1); 2D: A, B are coarse rows b, b + 1
@@ -125,15 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const TransferLaunch L) {
       const int32_t* T0 = &t[0];   // offset -1 in y
       const int32_t* T1 = &t[3];   // offset 0
       const int32_t* T2 = &t[6];   // offset +1
-      int32_t A[3], B[3], Cn[3], y0[4], y1[4], y0n[4], y1n[4];
-      pro_load(X, b0 * px, cc, px, true, lane, A);
-      pro_load(X, (b0 + 1) * px, cc, px, b0 + 1 <= nc + 1, lane, B);
-      if (HASY) {
-        ld4(Y, (2 * b0) * py + c, y0, act_y && 2 * b0 <= nf);
-        ld4(Y, (2 * b0 + 1) * py + c, y1, act_y && 2 * b0 + 1 <= nf);
-      } else {
+      int32_t A[3], B[3], Cn[3], y0n[4], y1n[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y0[q] = y1[q] = 0;
+      for (int q = 0; q < 3; ++q) {
+        A[q] = A2[q];
+        B[q] = B2[q];
       }
       for (int64_t J = b0; J < b1; ++J) {
         // loads of the next step first
@@ -277,43 +288,44 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const TransferLaunch L) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) colok[q] = C + q >= 1 && C + q <= nc;
   const bool act_y = C < py, act_z = C < pz;
+  const bool live = b0 < b1 && (ND == 2 || yc3 <= nc);
+  // a fine "line" is one fine row (2D) or the three fine rows 2 yc3 - 1 ..
+  // 2 yc3 + 1 of one fine plane (3D); share(T-index oz/oy, line, g)
+  constexpr int NR = ND == 3 ? 3 : 1;
+  int32_t Wm[NR][9], Wb[NR][9], Wmn[NR][9], Wbn[NR][9];
+  int32_t yv[4], yn[4];
+  auto load_line = [&](int64_t f, int32_t (&W)[NR][9]) {   // fine line index f
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int64_t row = ND == 3 ? f * sf + 2 * yc3 - 1 + r : f;
+      res_load(X, row * px, C, px, live && f <= nf + 1, lane, W[r]);
+    }
+  };
+  // the share of one fine line in a coarse output with line offset o
+  auto share = [&](int o, const int32_t (&W)[NR][9], int64_t (&g)[4]) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int32_t* T = ND == 3 ? &t[((o + 1) * 3 + r) * 3] : &t[(o + 1) * 3];
+      res_line(T, W[r], g);
+    }
+  };
+  auto load_yv = [&](int64_t b, int32_t (&V)[4]) {
+    if (HASY) ld4(Y, ((ND == 3 ? b * sc + yc3 : b)) * py + C, V, live && act_y && b <= nc);
+    else V[0] = V[1] = V[2] = V[3] = 0;
+  };
+  // the first lines are loaded before the epilogue reads the operands'
+  // metadata (they do not depend on it), so the two round trips overlap
+  int32_t Wt[NR][9];
+  load_line(2 * b0 - 1, Wt);                  // fine line 2 b0 - 1 (offset -1 of b0)
+  load_line(2 * b0, Wm);
+  load_line(2 * b0 + 1, Wb);
+  load_yv(b0, yv);
   Epi<PASS, HASY> E;
   E.init(L.op);
-  if (b0 < b1 && (ND == 2 || yc3 <= nc)) with_fast(E, [&](auto fast_tag) {
+  if (live) with_fast(E, [&](auto fast_tag) {
     constexpr int VAR = decltype(fast_tag)::value;
-    // a fine "line" is one fine row (2D) or the three fine rows 2 yc3 - 1 ..
-    // 2 yc3 + 1 of one fine plane (3D); share(T-index oz/oy, line, g)
-    constexpr int NR = ND == 3 ? 3 : 1;
-    int32_t Wm[NR][9], Wb[NR][9], Wmn[NR][9], Wbn[NR][9];
-    int32_t yv[4], yn[4];
-    auto load_line = [&](int64_t f, int32_t (&W)[NR][9]) {   // fine line index f
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int64_t row = ND == 3 ? f * sf + 2 * yc3 - 1 + r : f;
-        res_load(X, row * px, C, px, f <= nf + 1, lane, W[r]);
-      }
-    };
-    // the share of one fine line in a coarse output with line offset o
-    auto share = [&](int o, const int32_t (&W)[NR][9], int64_t (&g)[4]) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int32_t* T = ND == 3 ? &t[((o + 1) * 3 + r) * 3] : &t[(o + 1) * 3];
-        res_line(T, W[r], g);
-      }
-    };
-    auto load_yv = [&](int64_t b, int32_t (&V)[4]) {
-      if (HASY) ld4(Y, ((ND == 3 ? b * sc + yc3 : b)) * py + C, V, act_y && b <= nc);
-      else V[0] = V[1] = V[2] = V[3] = 0;
-    };
     int64_t carry[4] = {0, 0, 0, 0};
-    {
-      int32_t Wt[NR][9];
-      load_line(2 * b0 - 1, Wt);              // fine line 2 b0 - 1 (offset -1 of b0)
-      share(-1, Wt, carry);
-    }
-    load_line(2 * b0, Wm);
-    load_line(2 * b0 + 1, Wb);
-    load_yv(b0, yv);
+    share(-1, Wt, carry);
     for (int64_t I = b0; I < b1; ++I) {
       load_line(2 * I + 2, Wmn);
       load_line(2 * I + 3, Wbn);

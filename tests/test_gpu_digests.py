@@ -61,17 +61,28 @@ def test_digest_cases_present():
     assert "c2_4097sq" in GOLD and len(GOLD["c2_4097sq"]["levels"]) == 12
 
 
-def test_autotuned_shapes_keep_the_headline_digests():
-    """After mg_autotune picks per-level launch shapes on the 4097^2
-    hierarchy, the solve still matches the oracle's digests on every level."""
+@pytest.mark.parametrize("tuner", ["ops", "solve"])
+def test_autotuned_shapes_keep_the_headline_digests(tuner):
+    """After mg_autotune (launches timed one op at a time) or
+    mg_autotune_solve (whole solves timed) picks per-level launch shapes on
+    the 4097^2 hierarchy, the solve still matches the oracle's digests on
+    every level."""
     g = GOLD["c2_4097sq"]
     c = g["params"]
     p = P.mg_params_init(2, c["L"], c["w"], True, 1, 0, c["N"], POLICY[c["policy"]], c["eta"])
     H = P.Hierarchy(p)
+    f = [torch.from_numpy(W.manufactured_f(j, 2)).cuda() for j in range(1, c["L"] + 1)]
     try:
-        report = H.autotune(reps=3)
+        if tuner == "ops":
+            report = H.autotune(reps=3)
+        else:
+            for j in range(1, c["L"] + 1):
+                H.set_rhs(j, f[j - 1])
+            report = H.autotune_solve(reps=1)
+            for j, r in report.items():
+                assert r["star_us"] <= r["star_default_us"] and r["star_us"] > 0, (j, r)
         print(f"autotuned shapes: {report}", flush=True)
-        H.fmg_f64([torch.from_numpy(W.manufactured_f(j, 2)).cuda() for j in range(1, c["L"] + 1)])
+        H.fmg_f64(f)
         for lev, ref in g["levels"].items():
             for which, key in ((0, "x"), (2, "r")):
                 got = digest(H.get_vec(int(lev), which))

@@ -714,7 +714,14 @@ int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* o
  * at least 4 points; even values 2..1024, 0 = chosen from the grid size);
  * "diagnostics" = 1: hierarchies created while it is set keep the solve
  * diagnostics of mg_diag_read (0, the default: none, and no cost; read by
- * mg_hierarchy_bytes/create, which must see the same value).              */
+ * mg_hierarchy_bytes/create, which must see the same value);
+ * "fuse_relax_res" = 1: a 2D V-cycle's relaxation from zero and the
+ * residual after it (both nnqcomp, 32-bit storage, no diagnostics) run as
+ * one launch on the launched levels whose grids have at most
+ * "relax_res_max_n" points a side (default 255); 0 (the default): two
+ * launches (the same results; measured faster on MI355X, the fused kernel
+ * doing twice the arithmetic per point); "relax_res_rows" = rows one wave
+ * of that launch marches (0, the default: from the grid size).            */
 int bfp_tuning_set(const char* key, int value);
 
 /* Current value of a tuning key (the keys of bfp_tuning_set) into *value.

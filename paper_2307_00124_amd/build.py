@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libbfpmg.so")
 OBJ = os.path.join(HERE, "_build")
 # heaviest translation units first (they are compiled in parallel)
 SOURCES = ["k_star_x32.hip", "k_star_x16.hip", "k_star_x8.hip", "k_transfer2d.hip",
-           "k_transfer3d.hip", "k_point.hip", "k_exec.hip", "fp64mg.hip", "noalloc.hip", "k_tiles.hip", "k_band.hip", "k_star.hip", "k_transfer.hip",
+           "k_transfer3d.hip", "k_point.hip", "k_exec.hip", "fp64mg.hip", "noalloc.hip", "k_tiles.hip", "k_band.hip", "k_vcycle.hip", "k_star.hip", "k_transfer.hip",
            "api.cpp", "mg.cpp", "server.cpp", "estimate.cpp", "fe.cpp"]
 ARCH = os.environ.get("BFPMG_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

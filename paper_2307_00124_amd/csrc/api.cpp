@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bfpmg.h"
@@ -29,6 +30,12 @@ static int g_star3d_rows_large = 32, g_star3d_small_n = 64;
 // Coarse-level executor: programs are recorded for the levels whose grids
 // hold at most this many points (0 disables the executor).
 static int g_exec_max_points = 4096;
+static int g_fuse_relax_res = 0;
+static int g_relax_res_rows = 0;
+static int g_relax_res_max_n = 255;
+bool fuse_relax_res() { return g_fuse_relax_res != 0; }
+int relax_res_rows() { return g_relax_res_rows; }
+int relax_res_max_n() { return g_relax_res_max_n; }
 
 int exec_max_points() { return g_exec_max_points; }
 
@@ -309,11 +316,23 @@ static void fill_common(OpArgs* op, int w_out, const bfp_vec* x, const bfp_vec* 
   op->slots = g_slots;
 }
 
+// While set, a star op in saturate mode is prepared into *g_take_star
+// instead of launched (star_prepare_sat).
+static thread_local StarLaunch* g_take_star = nullptr;
+
 // Run one op in the requested mode: nnqcomp in one launch, qcomp as the
 // mu* pass followed by the output pass.
 template <typename L, typename F>
 static int run_modes(L& launch, int mode, hipStream_t s, F&& go) {
   if (g_rec) return record(launch, mode == BFP_SATURATE ? kModeSat : kExModeQ);
+  if constexpr (std::is_same<L, StarLaunch>::value) {
+    if (g_take_star) {
+      if (mode != BFP_SATURATE) return fail(BFP_EINVAL, "only saturate-mode ops are prepared");
+      launch.op.mode = kModeSat;
+      *g_take_star = launch;
+      return BFP_OK;
+    }
+  }
   int rc;
   if (mode == BFP_SATURATE) {
     launch.op.mode = kModeSat;
@@ -449,6 +468,18 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
     return run_modes(L, mode, s, [&](TransferLaunch& l) { return launch_transfer(l, s); });
   }
   return fail(BFP_EINVAL, "unknown stencil kind %d", A->kind);
+}
+
+int star_prepare_sat(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar* alpha,
+                     const bfp_scalar* beta, const bfp_vec* y, int w_out,
+                     const bfp_gamma* gamma, bfp_vec* z, StarLaunch* out) {
+  if (A && A->kind != BFP_STENCIL_A) return fail(BFP_EINVAL, "not a same-grid stencil");
+  StarLaunch L{};
+  g_take_star = &L;
+  const int rc = stencil_apply_impl(A, x, alpha, beta, y, w_out, BFP_SATURATE, gamma, z, nullptr, 0);
+  g_take_star = nullptr;
+  if (!rc) *out = L;
+  return rc;
 }
 
 int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta,
@@ -657,6 +688,17 @@ int bfp_tuning_set(const char* key, int value) {
     return BFP_OK;
   }
   if (k == "star2d_small_n") { g_star2d_small_n = value; return BFP_OK; }
+  if (k == "fuse_relax_res") {
+    if (value > 1) return fail(BFP_EINVAL, "fuse_relax_res is 0 or 1");
+    g_fuse_relax_res = value;
+    return BFP_OK;
+  }
+  if (k == "relax_res_max_n") { g_relax_res_max_n = value; return BFP_OK; }
+  if (k == "relax_res_rows") {
+    if (value > 1024) return fail(BFP_EINVAL, "relax_res_rows is at most 1024");
+    g_relax_res_rows = value;
+    return BFP_OK;
+  }
   if (k == "tiles2d_rows") {
     if (value > 1024) return fail(BFP_EINVAL, "tiles2d_rows is at most 1024");
     g_tiles_rows = value;
@@ -680,6 +722,9 @@ int bfp_tuning_get(const char* key, int* value) {
   else if (k == "star3d_rows") *value = g_star3d_rows_large;
   else if (k == "star3d_small_n") *value = g_star3d_small_n;
   else if (k == "tiles2d_rows") *value = g_tiles_rows;
+  else if (k == "fuse_relax_res") *value = g_fuse_relax_res;
+  else if (k == "relax_res_rows") *value = g_relax_res_rows;
+  else if (k == "relax_res_max_n") *value = g_relax_res_max_n;
   else return fail(BFP_EINVAL, "unknown tuning key %s", key);
   return BFP_OK;
 }

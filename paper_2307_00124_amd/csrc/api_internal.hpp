@@ -23,6 +23,13 @@ int stencil_apply_impl(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar*
                        const bfp_scalar* beta, const bfp_vec* y, int w_out, int mode,
                        const bfp_gamma* gamma, bfp_vec* z, hipStream_t s, int rows);
 
+// The launch description of a star op in saturate mode (the checks and
+// preparation of stencil_apply_impl), without launching it; outside a
+// recording only.
+int star_prepare_sat(const bfp_stencil* A, const bfp_vec* x, const bfp_scalar* alpha,
+                     const bfp_scalar* beta, const bfp_vec* y, int w_out,
+                     const bfp_gamma* gamma, bfp_vec* z, StarLaunch* out);
+
 // forced_mode = kModeNormMeta selects the one-pass normalization of a stored
 // block; -1 follows `mode`.
 int point_impl(const bfp_scalar* alpha, const bfp_vec* x, const bfp_scalar* beta,
@@ -44,6 +51,13 @@ void set_slots(int64_t* slots);
 bool diagnostics_on();
 // grids of at most this many points run inside recorded programs (0: never)
 int exec_max_points();
+// the V-cycle's relaxation and residual in one launch where they fit it
+// (tuning key "fuse_relax_res", default off) on grids up to
+// "relax_res_max_n" points a side, and its rows per wave ("relax_res_rows";
+// 0: automatic)
+bool fuse_relax_res();
+int relax_res_rows();
+int relax_res_max_n();
 // rows per wave of the 2D tiled stencil kernel (tuning key "tiles2d_rows"; 0: automatic)
 int tiles_rows();
 // Give every op of a recorded program the slots of its metadata blocks in

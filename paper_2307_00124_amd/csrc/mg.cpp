@@ -24,6 +24,7 @@
 #include "../../include/bfpmg.h"
 #include "api_internal.hpp"
 #include "kernels.hpp"
+#include "vcycle.hpp"
 
 using namespace bfpk;
 
@@ -241,6 +242,41 @@ int run_program(mg_hierarchy* h, const Program& pg, hipStream_t s,
   return BFP_OK;
 }
 
+// The relaxation y = Q(c2 A r + c1 r) and the residual s = Q(A y - r) of
+// level l in one launch, when the prepared ops fit the fused kernel
+// (*done = false otherwise: nothing was launched).
+int relax_res(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s, bool* done) {
+  Level& L = h->lv[l];
+  const mg_params& p = h->prm;
+  *done = false;
+  RelaxResLaunch F{};
+  const bfp_gamma g1 = g_norm(rin, p.c1), g2 = g_norm(rin, h->vres);
+  int rc = star_prepare_sat(&h->A, &rin, &p.c2, &p.c1, &rin, L.y.w, &g1, &L.y, &F.relax);
+  if (!rc) rc = star_prepare_sat(&h->A, &L.y, &kOne, &kMinusOne, &rin, L.s.w, &g2, &L.s, &F.res);
+  if (rc) return rc;
+  // only on grids up to relax_res_max_n a side: on larger grids the two
+  // separate kernels run near the bandwidth bound and the fused kernel
+  // (twice the arithmetic per point, halo rows computed again) is slower
+  // (measured on MI355X: 94 us against 76 us at 4095^2, 36 against 28 at
+  // 2047^2); on small grids it saves a launch, but the whole solve still
+  // measured 0.3-0.5% slower, so the fusion is off by default
+  const int64_t n = L.y.n;
+  if (n > relax_res_max_n() || !relax_res_fits(F.relax, F.res)) return BFP_OK;
+  int rows = relax_res_rows();
+  if (rows <= 0) rows = n >= 511 ? 4 : 2;
+  while (2 * relax_res_blocks(n, rows) > kMaxSlotBlocks) rows *= 2;
+  F.rows = rows;
+  F.slots = h->slots;
+  if ((rc = hip_check(launch_relax_res(F, s), "relaxation + residual"))) return rc;
+  // algorithmic bytes of the two ops (each input once, r once in the
+  // relaxation), one launch
+  h->bytes += pts(rin) * sz(rin) + pts(L.y) * sz(L.y);
+  h->bytes += pts(L.y) * sz(L.y) + pts(rin) * sz(rin) + pts(L.s) * sz(L.s);
+  h->launches += 1;
+  *done = true;
+  return BFP_OK;
+}
+
 // y = V(l, rin)
 int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
   Level& L = h->lv[l];
@@ -249,8 +285,17 @@ int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
   if (!recording() && l == h->Lc && h->prog[kPV].count && rin.mant == L.vr.mant &&
       rin.meta == L.vr.meta)
     return run_program(h, h->prog[kPV], s);
-  // relaxation from y = 0: y = c2 A r + c1 r
-  if ((rc = op_stencil(h, &h->A, rin, &p.c2, &p.c1, &rin, L.y, kRelax, mode_for(h, kRelax, false),
+  // relaxation from y = 0: y = c2 A r + c1 r; with one pre-smoothing step
+  // on a launched 2D level, optionally fused with the residual after it
+  // when both are nnqcomp (their exponents follow from r's metadata alone)
+  bool fused = false;
+  if (l > 1 && p.nu1 == 1 && p.ndim == 2 && fuse_relax_res() && !recording() && !h->diag &&
+      h->slots && mode_for(h, kRelax, false) == BFP_SATURATE &&
+      mode_for(h, kVRes, false) == BFP_SATURATE) {
+    if ((rc = relax_res(h, l, rin, s, &fused))) return rc;
+  }
+  if (!fused &&
+      (rc = op_stencil(h, &h->A, rin, &p.c2, &p.c1, &rin, L.y, kRelax, mode_for(h, kRelax, false),
                        g_norm(rin, p.c1), s)))
     return rc;
   const bfp_vec* last = nullptr;
@@ -267,8 +312,8 @@ int vcycle(mg_hierarchy* h, int l, const bfp_vec& rin, hipStream_t s) {
   }
   if (l > 1) {
     Level& C = h->lv[l - 1];
-    if ((rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
-                         kVRes, mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
+    if (!fused && (rc = op_stencil(h, &h->A, L.y, &kOne, &kMinusOne, &rin, L.s,
+                                   kVRes, mode_for(h, kVRes, false), g_norm(rin, h->vres), s)))
       return rc;
     if ((rc = op_stencil(h, &h->R, L.s, &kOne, nullptr, nullptr, C.vr,
                          kRestrict, mode_for(h, kRestrict, false), g_norm(L.s, kFour), s)))

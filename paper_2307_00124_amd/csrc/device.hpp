@@ -225,11 +225,15 @@ __device__ __forceinline__ int64_t axch(int64_t* p, int64_t v) {
 // are consumed), so the wait below covers them. Tickets are two-level: a
 // block counts itself in its set; the last block of a set counts the set at
 // the top level. One address never sees more than ~nblocks / kSets atomics.
+// Grids of at most kOneLevel blocks count at the top level directly (one
+// round trip fewer on the path of the last block).
+constexpr unsigned kOneLevel = 2 * kSets;
 __device__ __forceinline__ bool take_ticket(int64_t* meta, int64_t returned) {
   __shared__ volatile int64_t s_sink;
   s_sink = returned;
   wait_vmem();
   const unsigned nblk = gridDim.x * gridDim.y * gridDim.z;
+  if (nblk <= kOneLevel) return (unsigned)aadd(&meta[kMetaTicket], 1) == nblk - 1;
   const unsigned b = block_linear();
   const unsigned k = b % kSets;
   const unsigned in_set = (nblk - k + kSets - 1) / kSets;          // blocks of set k

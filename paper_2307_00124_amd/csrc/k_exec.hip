@@ -330,6 +330,15 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   }
 }
 
+// Points per thread and round of the star and pointwise ops: four in 2D;
+// in 3D (grids of at most 15^3 here) two in the single-hierarchy executor
+// and one in the batched one, which keeps the 3D op code within the
+// register file (more in flight spilled to scratch).
+template <int NT, int ND>
+constexpr int ex_rounds() {
+  return ND == 2 ? 4 : (NT > kBatchThreads ? 2 : 1);
+}
+
 template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32>
 __device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, const LdsMeta& ma,
                                      uintptr_t base) {
@@ -339,7 +348,7 @@ __device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, c
   int32_t t[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, DG, W32, 4>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, ex_rounds<NT, ND>()>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t b = (ND == 3 ? (int64_t)z * side + y : (int64_t)y) * px + x;
     int64_t g = (int64_t)t[0] * ldx<W32>(xs, b) + (int64_t)t[1] * ldx<W32>(xs, b - 1) +
@@ -429,7 +438,7 @@ __device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
   const int64_t px = L.px, side = L.n + 2;
-  ex_loop<NT, ND, PASS, HASY, DG, W32, 4>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, ex_rounds<NT, ND>()>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
     return ldx<W32>(xs, row * px + x);
@@ -638,16 +647,19 @@ __device__ __forceinline__ void run_program(const ExecOp* __restrict__ ops, int 
   if (DG && t == 0 && pend.diag) diag_count(pend.diag, pend.dbin, pend.dsat, pend.nsat);
 }
 
-// DG: the program counts diagnostics (otherwise their code is compiled out)
+// DG: the program counts diagnostics (otherwise their code is compiled out).
+// One workgroup per launch: two waves per SIMD is all the occupancy there
+// is, so the compiler may use the whole register file (no spills). The
+// plain 32-bit op copy only in 2D (3D programs cover grids of at most 15^3).
 template <int ND, bool DG>
-__global__ __launch_bounds__(kExecThreads) void k_exec(const ExecOp* __restrict__ ops, int count,
+__global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_exec(const ExecOp* __restrict__ ops, int count,
                                                       int64_t* const* __restrict__ metas,
                                                       int nmeta, ExecRhs rhs) {
   // the right-hand-side pointers, for the program's conversions (read after
   // the program runner's first barrier)
   __shared__ const double* srhs[kMaxLevels];
   if (threadIdx.x < kMaxLevels) srhs[threadIdx.x] = rhs.p[threadIdx.x];
-  run_program<kExecThreads, ND, DG, !DG>(ops, count, metas, nmeta, 0, srhs);
+  run_program<kExecThreads, ND, DG, ND == 2 && !DG>(ops, count, metas, nmeta, 0, srhs);
 }
 
 template <int ND>

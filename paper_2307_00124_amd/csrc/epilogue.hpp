@@ -180,6 +180,11 @@ struct Epi {
         fast = op.abits + la <= 62;
       }
     }
+    // first qcomp pass: z* = h 2^D + l (h the term of larger exponent) fits
+    // int64 when |h| 2^D < 2^62 (bit bound of h from the host, |l| < 2^61),
+    // so its msb needs no 128-bit arithmetic
+    if (PASS == kQ1 && HASY) fast = (swap ? op.bbits : op.abits) + D <= 62;
+    if (PASS == kQ1 && !HASY) fast = 1;
     tmax = 0;
     tmin = 0;
     tsat = 0;
@@ -225,11 +230,13 @@ struct Epi {
   template <int VAR>
   __device__ __forceinline__ int64_t put(int64_t g, int32_t yv, bool inside) {
     if (PASS == kQ1) {
-      const int64_t a = mul_a(g);
+      const int64_t a = VAR == kVarFastA1 ? g : mul_a(g);
       int m;
       if (HASY) {
         const int64_t b = mul_b(yv);
-        m = swap ? msb_exact2(b, a, D) : msb_exact2(a, b, D);
+        const int64_t h = swap ? b : a, l = swap ? a : b;
+        if (VAR != kVarGen) m = msb64((int64_t)((uint64_t)h << (int)D) + l);
+        else m = msb_exact2(h, l, D);
       } else {
         m = msb64(a);
       }

@@ -685,17 +685,19 @@ typedef struct {
 } mg_tune_report;
 int mg_autotune(mg_hierarchy* h, int reps, void* stream, mg_tune_report* out);
 /* The same per-level shapes chosen by the time of whole FMG solves
- * (mg_fmg on h's current right-hand sides, median of three runs of `reps`
- * solves): from the finest level down, each level's star march length
- * (default, 1..64) and then its transfer march length (default, 1..32) is
- * tried with every other level at its current shape, and the fastest kept
- * (a shape replaces the incumbent only when it is at least 0.2% faster).
- * Every shape is so judged in the solve's own conditions (caches, the
- * coarse-level executor's tails, the neighbouring launches). The solve's
- * result does not depend on the shapes; h's blocks end as after mg_fmg.
- * Set the right-hand sides first. Synchronizes `stream`. out (nullable):
- * the chosen shapes, the solve time with each pick (star_us, transfer_us)
- * and with the default shape at that point of the search (*_default_us). */
+ * (mg_fmg on h's current right-hand sides): from the finest level down,
+ * each level's star march length (1..64) and then its transfer march
+ * length (1..32) is timed in turns with the incumbent (first the default
+ * shape; three runs of `reps` solves each, medians compared, so a clock
+ * drift during the search favours neither) with every other level at its
+ * current shape; a candidate replaces the incumbent when at least 0.3%
+ * faster. Every shape is so judged in the solve's own conditions (caches,
+ * the coarse-level executor's tails, the neighbouring launches). The
+ * solve's result does not depend on the shapes; h's blocks end as after
+ * mg_fmg. Set the right-hand sides first. Synchronizes `stream`. out
+ * (nullable): the chosen shapes, the solve time with each level's pick in
+ * its last comparison (star_us, transfer_us) and with the default shape in
+ * its first (*_default_us).                                               */
 int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* out);
 
 /* Launch-shape tuning (process-wide; results do not depend on it):

@@ -395,7 +395,7 @@ class FEHierarchy:
         self.L = L
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.fe_hierarchy_destroy(self.h)
             self.h = None
 
@@ -461,7 +461,7 @@ class Hierarchy:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:   # not at interpreter exit
             lib.mg_hierarchy_destroy(h)
             self.h = None
 
@@ -627,7 +627,7 @@ class Batch:
 
     def __del__(self):
         b = getattr(self, "b", None)
-        if b is not None and b.value:
+        if b is not None and b.value and lib is not None:
             lib.mg_batch_destroy(b)
             self.b = None
 
@@ -669,7 +669,7 @@ class Server:
 
     def __del__(self):
         s = getattr(self, "s", None)
-        if s is not None and s.value:
+        if s is not None and s.value and lib is not None:
             lib.mg_server_destroy(s)
             self.s = None
 

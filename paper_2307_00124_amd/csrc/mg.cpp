@@ -1160,37 +1160,49 @@ int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* o
   std::memset(&rep, 0, sizeof rep);
   rep.first_level = h->Lc + 1;
   rep.last_level = L;
-  // time of one FMG solve: median of three runs of `reps` solves
-  auto timed = [&](float* us) {
-    float t[3];
-    for (int k = 0; k < 3 && !rc; ++k) {
-      rc = mg_fmg(h, s);
-      if (!rc) rc = hip_check(hipEventRecord(e0, s), "event record");
-      for (int i = 0; i < reps && !rc; ++i) rc = mg_fmg(h, s);
-      if (!rc) rc = hip_check(hipEventRecord(e1, s), "event record");
-      if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
-      float ms = 0;
-      if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
-      t[k] = ms * 1000.0f / reps;
-    }
-    if (rc) return;
+  // time of one FMG solve over one run of `reps` solves (after one more)
+  auto timed1 = [&](float* us) {
+    if (!rc) rc = mg_fmg(h, s);
+    if (!rc) rc = hip_check(hipEventRecord(e0, s), "event record");
+    for (int i = 0; i < reps && !rc; ++i) rc = mg_fmg(h, s);
+    if (!rc) rc = hip_check(hipEventRecord(e1, s), "event record");
+    if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
+    float ms = 0;
+    if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+    *us = ms * 1000.0f / reps;
+  };
+  auto median3 = [](float* t) {
     std::sort(t, t + 3);
-    *us = t[1];
+    return t[1];
   };
   const int cands[] = {1, 2, 4, 8, 16, 32, 64};
-  // one kind (0 star, 1 transfer) on level j: keep the fastest shape
+  // one kind (0 star, 1 transfer) on level j: every candidate is timed in
+  // turns with the incumbent (three runs each, medians compared), so a
+  // drift of the clock during the search favours neither; a candidate
+  // replaces the incumbent when at least 0.3% faster
   auto search = [&](int kind, int j, int maxc, int32_t* pick_out, float* best_out,
                     float* default_out) {
-    set_level_rows(kind, nd, j, 0);
-    float best = 0, t = 0;
-    timed(&best);
-    *default_out = best;
     int pick = 0;
+    float best = 0;
     for (int c : cands) {
       if (rc || c > maxc) break;
-      set_level_rows(kind, nd, j, c);
-      timed(&t);
-      if (!rc && t < best * 0.998f) { best = t; pick = c; }
+      float ti[3], tc[3];
+      for (int k = 0; k < 3 && !rc; ++k) {
+        set_level_rows(kind, nd, j, pick);
+        timed1(&ti[k]);
+        set_level_rows(kind, nd, j, c);
+        timed1(&tc[k]);
+      }
+      if (rc) break;
+      const float mi = median3(ti), mc = median3(tc);
+      if (pick == 0 && c == cands[0]) *default_out = mi;
+      if (best == 0) best = mi;
+      if (mc < mi * 0.997f) {
+        pick = c;
+        best = mc;
+      } else {
+        best = mi;
+      }
     }
     if (rc) return;
     set_level_rows(kind, nd, j, pick);

@@ -60,7 +60,7 @@ def parse():
                     help="problems solved one at a time for the batched comparison")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default launch shapes (no mg_autotune before timing)")
+                    help="keep the default launch shapes (no autotuning before timing)")
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="oracle processes of the CPU baseline (at most the cores available)")
     ap.add_argument("--no-extras", action="store_true",
@@ -171,7 +171,8 @@ def main():
             H = make(args.w)
             for j in range(1, L + 1):
                 H.set_rhs(j, f[j], stream)
-            H.autotune_solve(reps=3, stream=stream)
+            if not args.no_autotune:
+                H.autotune_solve(reps=3, stream=stream)
             run = lambda: H.fmg_f64(rhs, stream)
         else:
             F = P.FP64MG(P.mg_params_init(2, L, 32, True, 1, 0, 2, P.MG_POLICY_NN_IR_FIRST_Q, 23))

@@ -119,19 +119,46 @@ __global__ __launch_bounds__(kBlock) void k_f64_nu(const ConvertLaunch L) {
   const int64_t items = row_items(n, L.ndim);
   int64_t best = INT64_MIN;
   bool bad = false;
+  auto take = [&](double x) {
+    int64_t z, e;
+    bool fin;
+    if (f64_parts(x, z, e, fin)) {
+      const int64_t nu = msb64(z) + e;
+      best = nu > best ? nu : best;
+    }
+    bad |= !fin;
+  };
+  // 16-byte loads: a row starting at an odd element (rows alternate, the
+  // row length n + 2 being odd) is read in pairs shifted by one column, so
+  // every pair is aligned; each interior column still lies in exactly one
+  // thread's four columns, and a pair is read only when both of its
+  // columns lie in the row
+  const bool al16 = ((uintptr_t)src & 15) == 0;
   for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
     const int64_t rr = interior_row(it / nchunk, n, L.ndim);
     const int64_t c0 = (it % nchunk) * 1024 + threadIdx.x * 4;
-    for (int k = 0; k < 4; ++k) {
-      const int64_t c = c0 + k;
-      if (c < 1 || c > n) continue;
-      int64_t z, e;
-      bool fin;
-      if (f64_parts(src[rr * side + c], z, e, fin)) {
-        const int64_t nu = msb64(z) + e;
-        best = nu > best ? nu : best;
+    const int64_t g0 = rr * side;
+    if (al16) {
+      const int64_t cs = c0 - (g0 & 1);
+      double v[4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t p = cs + 2 * h;
+        const bool ok = p >= 0 && p + 1 <= n + 1;
+        const double2 q = *reinterpret_cast<const double2*>(src + (ok ? g0 + p : 0));
+        v[2 * h] = ok ? q.x : 0.0;
+        v[2 * h + 1] = ok ? q.y : 0.0;
       }
-      bad |= !fin;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t c = cs + k;
+        if (c >= 1 && c <= n) take(v[k]);
+      }
+    } else {
+      for (int k = 0; k < 4; ++k) {
+        const int64_t c = c0 + k;
+        if (c >= 1 && c <= n) take(src[g0 + c]);
+      }
     }
   }
   if (bad) atomicOr((unsigned long long*)&L.meta[kMetaFlags], 1ull);

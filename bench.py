@@ -71,11 +71,12 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: leave the environment's)")
-    ap.add_argument("--only", choices=["all", "kernel", "copy", "solve", "fp64", "coarse",
-                                       "tiles"],
+    ap.add_argument("--only", choices=["all", "kernel", "copy", "streamcopy", "solve", "fp64",
+                                       "coarse", "tiles"],
                     default="all",
                     help="kernel: only the dominant-kernel loop (for profiler runs); copy: only "
-                         "a plain 1 GiB device copy (counter calibration); solve: only --warmup + "
+                         "a plain 1 GiB device copy (counter calibration); streamcopy: only the "
+                         "library's streaming copy of 1 GiB; solve: only --warmup + "
                          "--steps headline solves (autotuned shapes), nothing else; fp64: only "
                          "the FP64 comparator's solves; coarse: only FMG solves of the 65^2 grid "
                          "(6 levels, all of them inside the coarse-level executor); tiles: only "
@@ -122,6 +123,26 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "launches": 5}))
+        return
+    if args.only == "streamcopy":
+        # the library's streaming copy of 1 GiB, plain then non-temporal, for the profiler
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        out = {}
+        for nt in (False, True):
+            for _ in range(2):
+                P.bfp_stream_copy(a, b, nt, stream)
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            for _ in range(10):
+                P.bfp_stream_copy(a, b, nt, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 100.0
+            out["nt" if nt else "plain"] = {"avg_us": round(us, 1),
+                                            "gbs": round(2 * a.numel() * 4 / (us * 1e-6) / 1e9, 1)}
+        print(json.dumps({"stream_copy_bytes_each_way": a.numel() * 4, **out}))
         return
 
     L = args.level
@@ -298,6 +319,13 @@ def main():
     tcp = time_kernel(lambda: cb.copy_(ca), args.kernel_reps)
     stencils["copy_8x4095sq_int32"] = {"avg_us": round(tcp, 2), "bytes": dof * 32.0,
                                        "gbs": round(dof * 32.0 / (tcp * 1e-6) / 1e9, 1)}
+    # the library's own streaming copy (16-byte words, four in flight per
+    # thread; plain and non-temporal): the hand-written bandwidth reference
+    for nt in (False, True):
+        tsc = time_kernel(lambda: P.bfp_stream_copy(ca, cb, nt, stream), args.kernel_reps)
+        stencils["stream_copy" + ("_nt" if nt else "") + "_8x4095sq_int32"] = {
+            "avg_us": round(tsc, 2), "bytes": dof * 32.0,
+            "gbs": round(dof * 32.0 / (tsc * 1e-6) / 1e9, 1)}
     del ca, cb
     del xs, zs
     if not args.no_3d:

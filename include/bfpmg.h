@@ -212,6 +212,18 @@ int bfp_sub(const bfp_vec* x, const bfp_vec* y, int w_out, int mode, const bfp_g
  * before the first call (they are left zero after every call).            */
 int bfp_dot(const bfp_vec* x, const bfp_vec* y, int64_t* out_dev, void* stream);
 
+/* Plain device copy of `bytes` from src_dev to dst_dev (both 16-byte
+ * aligned, bytes a multiple of 16; the ranges must not overlap) with
+ * 16-byte loads and stores, grid-strided, "stream_copy_per_thread" (4 or
+ * 8, default 4) words in flight per thread on at most
+ * "stream_copy_blocks" (default 1024) workgroups (nontemporal = 1:
+ * non-temporal loads and stores). Not a BFP operation: the streaming-
+ * bandwidth reference that the roofline fractions of the BFP kernels are
+ * read against. Asynchronous on `stream`. BFP_EINVAL on a bad size,
+ * alignment or NULL pointer (bytes = 0: nothing to do).                   */
+int bfp_stream_copy(const void* src_dev, void* dst_dev, int64_t bytes, int nontemporal,
+                    void* stream);
+
 /* ------------------------------------------------ a7, a8: requantization */
 
 /* out = qcomp of the copy of in to w_out bits (normalized, floor): one pass,
@@ -717,6 +729,8 @@ int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* o
  * "diagnostics" = 1: hierarchies created while it is set keep the solve
  * diagnostics of mg_diag_read (0, the default: none, and no cost; read by
  * mg_hierarchy_bytes/create, which must see the same value);
+ * "stream_copy_blocks" / "stream_copy_per_thread": the shape of
+ * bfp_stream_copy (values >= 1);
  * "fuse_relax_res" = 1: a 2D V-cycle's relaxation from zero and the
  * residual after it (both nnqcomp, 32-bit storage, no diagnostics) run as
  * one launch on the launched levels whose grids have at most

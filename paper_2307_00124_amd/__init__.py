@@ -262,6 +262,17 @@ def bfp_dot(x: Vec, y: Vec, out: torch.Tensor, stream=None) -> None:
     check(lib.bfp_dot(C.byref(x.c), C.byref(y.c), _ptr(out), _stream(stream)), "bfp_dot")
 
 
+def bfp_stream_copy(src: torch.Tensor, dst: torch.Tensor, nontemporal: bool = False,
+                    stream=None) -> None:
+    """bfp_stream_copy: dst <- src (whole tensors of equal byte size), the
+    library's plain streaming copy (the bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("src and dst must be device tensors of the same size in bytes")
+    check(lib.bfp_stream_copy(_ptr(src), _ptr(dst), nbytes, int(nontemporal), _stream(stream)),
+          "bfp_stream_copy")
+
+
 def bfp_normalize(x: Vec, w_out: int, out: Vec, stream=None) -> None:
     check(lib.bfp_normalize(C.byref(x.c), w_out, C.byref(out.c), _stream(stream)),
           "bfp_normalize")

@@ -126,6 +126,7 @@ SIGNATURES = {
                      P(bfp_gamma), P(bfp_vec), VP]),
     "bfp_sub": (I, [P(bfp_vec), P(bfp_vec), I, I, P(bfp_gamma), P(bfp_vec), VP]),
     "bfp_dot": (I, [P(bfp_vec), P(bfp_vec), VP, VP]),
+    "bfp_stream_copy": (I, [VP, VP, C.c_int64, I, VP]),
     "bfp_normalize": (I, [P(bfp_vec), I, P(bfp_vec), VP]),
     "bfp_saturate_truncate": (I, [P(bfp_vec), I, P(bfp_gamma), P(bfp_vec), VP]),
     "bfp_cheby_coeffs": (I, [I64, I64, I64, I64, I64, I64, I, P(bfp_scalar), P(bfp_scalar)]),

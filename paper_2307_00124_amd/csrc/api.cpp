@@ -33,6 +33,8 @@ static int g_exec_max_points = 4096;
 static int g_fuse_relax_res = 0;
 static int g_relax_res_rows = 0;
 static int g_relax_res_max_n = 255;
+static int g_stream_copy_blocks = 1024;
+static int g_stream_copy_per_thread = 4;
 bool fuse_relax_res() { return g_fuse_relax_res != 0; }
 int relax_res_rows() { return g_relax_res_rows; }
 int relax_res_max_n() { return g_relax_res_max_n; }
@@ -694,6 +696,11 @@ int bfp_tuning_set(const char* key, int value) {
     return BFP_OK;
   }
   if (k == "relax_res_max_n") { g_relax_res_max_n = value; return BFP_OK; }
+  if (k == "stream_copy_blocks" || k == "stream_copy_per_thread") {
+    if (value < 1) return fail(BFP_EINVAL, "value out of range");
+    (k == "stream_copy_blocks" ? g_stream_copy_blocks : g_stream_copy_per_thread) = value;
+    return BFP_OK;
+  }
   if (k == "relax_res_rows") {
     if (value > 1024) return fail(BFP_EINVAL, "relax_res_rows is at most 1024");
     g_relax_res_rows = value;
@@ -725,6 +732,8 @@ int bfp_tuning_get(const char* key, int* value) {
   else if (k == "fuse_relax_res") *value = g_fuse_relax_res;
   else if (k == "relax_res_rows") *value = g_relax_res_rows;
   else if (k == "relax_res_max_n") *value = g_relax_res_max_n;
+  else if (k == "stream_copy_blocks") *value = g_stream_copy_blocks;
+  else if (k == "stream_copy_per_thread") *value = g_stream_copy_per_thread;
   else return fail(BFP_EINVAL, "unknown tuning key %s", key);
   return BFP_OK;
 }
@@ -747,6 +756,20 @@ int bfp_vec_assign(bfp_vec* v, int64_t exp, void* stream) {
   L.xbits = L.zbits = v->storage_bits;
   L.ybits = 32;
   return hip_check(launch_point(L, (hipStream_t)stream), "bfp_vec_assign");
+}
+
+int bfp_stream_copy(const void* src_dev, void* dst_dev, int64_t bytes, int nontemporal,
+                    void* stream) {
+  if (bytes < 0 || bytes % 16) return fail(BFP_EINVAL, "bytes must be a non-negative multiple of 16");
+  if (bytes == 0) return BFP_OK;
+  if (!src_dev || !dst_dev) return fail(BFP_EINVAL, "NULL pointer");
+  if (((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15)
+    return fail(BFP_EINVAL, "pointers must be 16-byte aligned");
+  if (nontemporal != 0 && nontemporal != 1) return fail(BFP_EINVAL, "nontemporal is 0 or 1");
+  return hip_check(launch_stream_copy(src_dev, dst_dev, bytes, nontemporal == 1,
+                                      g_stream_copy_blocks, g_stream_copy_per_thread,
+                                      (hipStream_t)stream),
+                   "stream copy");
 }
 
 int bfp_dot(const bfp_vec* x, const bfp_vec* y, int64_t* out_dev, void* stream) {

@@ -51,6 +51,9 @@ void set_slots(int64_t* slots);
 bool diagnostics_on();
 // grids of at most this many points run inside recorded programs (0: never)
 int exec_max_points();
+// plain streaming copy of `bytes` (a multiple of 16, 16-byte aligned)
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, bool nontemporal,
+                              int max_blocks, int per_thread, hipStream_t s);
 // the V-cycle's relaxation and residual in one launch where they fit it
 // (tuning key "fuse_relax_res", default off) on grids up to
 // "relax_res_max_n" points a side, and its rows per wave ("relax_res_rows";

@@ -214,6 +214,55 @@ __global__ __launch_bounds__(kBlock) void k_f64_conv(const ConvertLaunch L) {
   finish_outputs(tmax, tmin, 0, L.meta, eq + L.log2_scale);
 }
 
+// ------------------------------------------------- streaming copy -------
+
+// A plain device copy of 16-byte words, CU in flight per thread and
+// grid-strided: the streaming-bandwidth reference the BFP kernels are
+// measured against (NT: non-temporal loads and stores).
+template <bool NT, int CU>
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const v4i32* __restrict__ src,
+                                                      v4i32* __restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n16; i0 += CU * stride) {
+    v4i32 v[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+      const int64_t i = i0 + u * stride;
+      const v4i32* p = src + (i < n16 ? i : 0);
+      v[u] = NT ? __builtin_nontemporal_load(p) : *p;
+    }
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n16) {
+        if (NT) __builtin_nontemporal_store(v[u], dst + i);
+        else dst[i] = v[u];
+      }
+    }
+  }
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, bool nontemporal,
+                              int max_blocks, int per_thread, hipStream_t s) {
+  const int64_t n16 = bytes / 16;
+  if (n16 <= 0) return hipSuccess;
+  const int cu = per_thread >= 8 ? 8 : 4;
+  const int64_t per_block = (int64_t)kBlock * cu;
+  int64_t blocks = (n16 + per_block - 1) / per_block;
+  if (blocks > max_blocks) blocks = max_blocks;
+  const v4i32* a = static_cast<const v4i32*>(src);
+  v4i32* b = static_cast<v4i32*>(dst);
+  const dim3 g((unsigned)blocks), t(kBlock);
+  if (nontemporal) {
+    if (cu == 8) hipLaunchKernelGGL((k_stream_copy<true, 8>), g, t, 0, s, a, b, n16);
+    else hipLaunchKernelGGL((k_stream_copy<true, 4>), g, t, 0, s, a, b, n16);
+  } else {
+    if (cu == 8) hipLaunchKernelGGL((k_stream_copy<false, 8>), g, t, 0, s, a, b, n16);
+    else hipLaunchKernelGGL((k_stream_copy<false, 4>), g, t, 0, s, a, b, n16);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_from_f64(const ConvertLaunch& L, hipStream_t s) {
   const unsigned blocks = grid_for(row_items(L.n, L.ndim));
   hipLaunchKernelGGL(k_f64_nu, dim3((unsigned)blocks), dim3(kBlock), 0, s, L);

@@ -158,3 +158,14 @@ def test_tuning_keys_and_autotuner_arguments():
     r = abi.mg_tune_report()
     assert lib.mg_autotune_solve(None, 3, None, C.byref(r)) == abi.BFP_EINVAL
     assert lib.mg_autotune(None, 3, None, C.byref(r)) == abi.BFP_EINVAL
+
+
+def test_stream_copy_argument_errors():
+    """bfp_stream_copy checks size, alignment and pointers on the host."""
+    lib = P.lib
+    assert lib.bfp_stream_copy(None, None, 0, 0, None) == abi.BFP_OK
+    assert lib.bfp_stream_copy(0x1000, 0x2000, 24, 0, None) == abi.BFP_EINVAL
+    assert lib.bfp_stream_copy(0x1008, 0x2000, 32, 0, None) == abi.BFP_EINVAL
+    assert lib.bfp_stream_copy(None, 0x2000, 32, 0, None) == abi.BFP_EINVAL
+    assert lib.bfp_stream_copy(0x1000, 0x2000, 32, 2, None) == abi.BFP_EINVAL
+    assert lib.bfp_stream_copy(0x1000, 0x2000, -16, 0, None) == abi.BFP_EINVAL

@@ -415,3 +415,18 @@ def test_full_size_residual_sampled():
         assert int(ref.m[1, 1]) == int(rm[i, j]), (i, j)
     assert meta[P.BFP_META_MAX] == max(0, int(rm.max()))
     assert meta[P.BFP_META_MIN] == min(0, int(rm.min()))
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 48, (1 << 22) + 16 * 1001])
+@pytest.mark.parametrize("nt", [False, True])
+def test_stream_copy(nbytes, nt):
+    """bfp_stream_copy (the bandwidth reference) copies every byte, grid
+    strides and ragged tails included, and writes nothing beyond."""
+    g = torch.Generator(device="cpu").manual_seed(nbytes)
+    src = torch.randint(-(1 << 31), 1 << 31, (nbytes // 4,), dtype=torch.int64, generator=g)
+    src = src.to(torch.int32).cuda()
+    dst = torch.full((nbytes // 4 + 64,), 7, dtype=torch.int32, device="cuda")
+    P.bfp_stream_copy(src, dst[: nbytes // 4], nt)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[: nbytes // 4], src)
+    assert bool((dst[nbytes // 4:] == 7).all())

@@ -128,12 +128,21 @@ struct PendingDiag {
   int64_t nsat;
 };
 
-// Workgroup reductions: per-wave partials (DPP) in LDS, then every wave
-// reduces the partials itself. The first qcomp pass needs mu* at once (one
-// barrier, then each wave writes the same mu* into the output's row); an
-// output pass only leaves its partials, published after the program loop's
-// barrier (the one that also makes the op's stores visible), so an op
-// costs one barrier per pass.
+// Workgroup reductions: per-wave partials (DPP) in LDS.
+// Single-hierarchy programs (latency-bound: one workgroup on the GPU) let
+// every wave reduce the partials itself: the first qcomp pass needs mu* at
+// once (one barrier, then each wave writes the same mu* into the output's
+// row); an output pass only leaves its partials, published after the
+// program loop's barrier (the one that also makes the op's stores
+// visible), so an op costs one barrier per pass and no wave waits behind a
+// serial tail. Batched programs (many workgroups per CU: throughput-bound)
+// keep the cheaper form: wave 0 alone reduces after a barrier and writes
+// the row before the next barrier.
+template <int NT>
+constexpr bool ex_latency_form() {
+  return NT > kBatchThreads;
+}
+
 template <int NT, int PASS, bool HASY, bool DG>
 __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY, DG>& E, const LdsMeta& ma) {
   constexpr int kW = NT / 64;
@@ -144,11 +153,19 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY, DG>& E, const Ld
     const int32_t m = wave_max32((int32_t)E.tmu);
     if (lane == 0) r[wave] = m;
     __syncthreads();
-    int32_t b = 1;
+    if constexpr (ex_latency_form<NT>()) {
+      int32_t b = 1;
 #pragma unroll
-    for (int k = 0; k < kW; ++k) b = r[k] > b ? r[k] : b;
-    if (lane == 0) zm[kMetaMu] = b;
-    wave_sync_lds();
+      for (int k = 0; k < kW; ++k) b = r[k] > b ? r[k] : b;
+      if (lane == 0) zm[kMetaMu] = b;
+      wave_sync_lds();
+    } else {
+      if (wave == 0) {
+        const int32_t b = wave_max32(lane < kW ? r[lane] : 1);
+        if (lane == 0) zm[kMetaMu] = b;
+      }
+      __syncthreads();   // the second pass reads mu* at once
+    }
   } else {
     Fin& f = *ma.fin;
     int32_t* r = ma.red + f.par * 3 * kW;
@@ -158,20 +175,40 @@ __device__ __forceinline__ void ex_finish(const Epi<PASS, HASY, DG>& E, const Ld
       r[kW + wave] = b;
       r[2 * kW + wave] = c;
     }
-    f.z = &zm;
-    f.kind = kFinOut;
-    f.eo = E.R.eo;
-    f.diag = DG ? E.diag : nullptr;
-    f.dbin = E.dbin;
-    f.dsat = E.dsat;
+    if constexpr (ex_latency_form<NT>()) {
+      f.z = &zm;
+      f.kind = kFinOut;
+      f.eo = E.R.eo;
+      f.diag = DG ? E.diag : nullptr;
+      f.dbin = E.dbin;
+      f.dsat = E.dsat;
+    } else {
+      __syncthreads();
+      if (wave == 0) {
+        const bool in = lane < kW;
+        const int32_t mx = wave_max32(in ? r[lane] : 0);
+        const int32_t mn = wave_min32(in ? r[kW + lane] : 0);
+        const int32_t st = wave_sum32(in ? r[2 * kW + lane] : 0);
+        if (lane == 0) {
+          zm[kMetaMax] = mx;
+          zm[kMetaMin] = mn;
+          zm[kMetaSat] = st;
+          zm[kMetaExp] = E.R.eo;
+          if (DG && E.diag) *ma.pend = PendingDiag{E.diag, E.dbin, E.dsat, st};
+        }
+      }
+      // the program loop's barrier follows before any reader
+    }
   }
 }
 
-// Publish the previous op's metadata (after the program loop's barrier).
+// Publish the previous op's metadata (after the program loop's barrier;
+// latency form only).
 template <int NT, bool DG>
 __device__ __forceinline__ void ex_publish(Fin& f, const int32_t* red, PendingDiag& pend) {
   constexpr int kW = NT / 64;
   const int lane = threadIdx.x & 63;
+  if (f.kind == kFinNone) return;
   if (f.kind == kFinOut) {
     const int32_t* r = red + f.par * 3 * kW;
     int32_t mx = 0, mn = 0, st = 0;
@@ -236,15 +273,17 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
     int64_t g[U], zo[U];
     int32_t yv[U];
     bool ok[U];
-    // rounds holding a point of this wave (the rest are skipped uniformly)
-    const int w0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63;
+    // rounds holding a point of this wave (the rest are skipped uniformly;
+    // latency form only: in batched programs every round keeps its loads
+    // in one straight run)
+    const int w0 = ex_latency_form<NT>() ? __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63 : 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ok[u] = false;
       g[u] = 0;
       zo[u] = 0;
       yv[u] = 0;
-      if (w0 + u * NT >= tot) continue;
+      if (ex_latency_form<NT>() && w0 + u * NT >= tot) continue;
       const int i = threadIdx.x + u * NT;
       int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
       ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
@@ -260,7 +299,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (w0 + u * NT < tot) E1.template put<kVarGen>(g[u], yv[u], ok[u]);
+      if (!ex_latency_form<NT>() || w0 + u * NT < tot) E1.template put<kVarGen>(g[u], yv[u], ok[u]);
     ex_finish<NT>(E1, ma);   // mu*, after one barrier
     Epi<kOut, HASY, DG> E2;
     E2.init(q2, ma);
@@ -268,7 +307,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
       constexpr int VAR = decltype(var_tag)::value;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (w0 + u * NT >= tot) continue;
+        if (ex_latency_form<NT>() && w0 + u * NT >= tot) continue;
         const int64_t v = E2.template put<VAR>(g[u], yv[u], ok[u]);
         if (ok[u]) stv<W32>(zp, zbits, zo[u], v);
       }
@@ -289,8 +328,8 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
   const int64_t side = n + 2;
   auto body = [&](auto var_tag) {
     constexpr int VAR = decltype(var_tag)::value;
-    const int w0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63;
-    for (int r0 = 0; w0 + r0 < tot; r0 += U * NT) {
+    const int w0 = ex_latency_form<NT>() ? __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63 : 0;
+    for (int r0 = 0; (ex_latency_form<NT>() ? w0 : (int)threadIdx.x) + r0 < tot; r0 += U * NT) {
       const int i0 = threadIdx.x + r0;
       int64_t g[U], zo[U];
       int32_t yv[U];
@@ -301,7 +340,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
         g[u] = 0;
         zo[u] = 0;
         yv[u] = 0;
-        if (w0 + r0 + u * NT >= tot) continue;
+        if (ex_latency_form<NT>() && w0 + r0 + u * NT >= tot) continue;
         const int i = i0 + u * NT;
         int x = (i & M) + 1, y = ((i >> lg) & M) + 1, z = ND == 3 ? (i >> (2 * lg)) + 1 : 0;
         ok[u] = i < tot && x <= n && y <= n && (ND == 2 || z <= n);
@@ -317,7 +356,7 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (w0 + r0 + u * NT >= tot) continue;
+        if (ex_latency_form<NT>() && w0 + r0 + u * NT >= tot) continue;
         const int64_t v = E.template put<VAR>(g[u], yv[u], ok[u]);
         if (PASS != kQ1 && ok[u]) stv<W32>(zp, zbits, zo[u], v);
       }
@@ -445,15 +484,20 @@ __device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op,
   });
 }
 
-// (the metadata is published after the loop's barrier, like an op's)
+// (latency form: the metadata is published after the loop's barrier, like
+// an op's)
 template <int NT>
 __device__ __forceinline__ void ex_zero(const ZeroOp& Z, MetaRow* zm, Fin& fin, uintptr_t base) {
   uint4* p = static_cast<uint4*>(rel(Z.mant, base));
   const int64_t n16 = Z.bytes / 16;
   for (int64_t i = threadIdx.x; i < n16; i += NT) p[i] = make_uint4(0, 0, 0, 0);
-  fin.z = zm;
-  fin.kind = kFinZero;
-  fin.eo = Z.exp;
+  if constexpr (ex_latency_form<NT>()) {
+    fin.z = zm;
+    fin.kind = kFinZero;
+    fin.eo = Z.exp;
+  } else if (threadIdx.x < kExMetaF) {
+    (*zm)[threadIdx.x] = threadIdx.x == kMetaExp ? Z.exp : (threadIdx.x == kMetaMu ? 1 : 0);
+  }
 }
 
 

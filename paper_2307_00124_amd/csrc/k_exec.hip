@@ -371,11 +371,12 @@ __device__ __forceinline__ void ex_loop(const OpArgs& op, const LdsMeta& ma, uin
 
 // Points per thread and round of the star and pointwise ops: four in 2D;
 // in 3D (grids of at most 15^3 here) two in the single-hierarchy executor
-// and one in the batched one, which keeps the 3D op code within the
-// register file (more in flight spilled to scratch).
-template <int NT, int ND>
+// and one in the batched one and in the programs that count diagnostics,
+// which keeps the 3D op code within the register file (more in flight
+// spilled to scratch).
+template <int NT, int ND, bool DG>
 constexpr int ex_rounds() {
-  return ND == 2 ? 4 : (NT > kBatchThreads ? 2 : 1);
+  return ND == 2 ? 4 : (NT > kBatchThreads && !DG ? 2 : 1);
 }
 
 template <int NT, int ND, int PASS, bool HASY, bool DG, bool W32>
@@ -387,7 +388,7 @@ __device__ __forceinline__ void ex_star(const StarLaunch& L, const OpArgs& op, c
   int32_t t[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) t[k] = L.taps[k];
-  ex_loop<NT, ND, PASS, HASY, DG, W32, ex_rounds<NT, ND>()>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, ex_rounds<NT, ND, DG>()>(op, ma, base, n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t b = (ND == 3 ? (int64_t)z * side + y : (int64_t)y) * px + x;
     int64_t g = (int64_t)t[0] * ldx<W32>(xs, b) + (int64_t)t[1] * ldx<W32>(xs, b - 1) +
@@ -477,7 +478,7 @@ __device__ __forceinline__ void ex_point(const PointLaunch& L, const OpArgs& op,
                                      uintptr_t base) {
   const Src xs = src_of(L.x, L.xbits, base);
   const int64_t px = L.px, side = L.n + 2;
-  ex_loop<NT, ND, PASS, HASY, DG, W32, ex_rounds<NT, ND>()>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
+  ex_loop<NT, ND, PASS, HASY, DG, W32, ex_rounds<NT, ND, DG>()>(op, ma, base, (int)L.n, L.y, L.ybits, L.py, L.z, L.zbits, L.pz,
                           [&](int z, int y, int x) -> int64_t {
     const int64_t row = ND == 3 ? (int64_t)z * side + y : (int64_t)y;
     return ldx<W32>(xs, row * px + x);

@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: leave the environment's)")
     ap.add_argument("--only", choices=["all", "kernel", "copy", "streamcopy", "solve", "fp64",
-                                       "coarse", "tiles"],
+                                       "coarse", "tiles", "fe"],
                     default="all",
                     help="kernel: only the dominant-kernel loop (for profiler runs); copy: only "
                          "a plain 1 GiB device copy (counter calibration); streamcopy: only the "
@@ -80,7 +80,8 @@ def parse():
                          "--steps headline solves (autotuned shapes), nothing else; fp64: only "
                          "the FP64 comparator's solves; coarse: only FMG solves of the 65^2 grid "
                          "(6 levels, all of them inside the coarse-level executor); tiles: only "
-                         "the tiled residual loop (T = 64, 4095^2)")
+                         "the tiled residual loop (T = 64, 4095^2); fe: only the finite-element "
+                         "model problems")
     return ap.parse_args()
 
 
@@ -123,6 +124,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "launches": 5}))
+        return
+    if args.only == "fe":
+        print(json.dumps({"only": "fe", "finite_elements": bench_fe(P, np, torch, stream, ev)}))
         return
     if args.only == "streamcopy":
         # the library's streaming copy of 1 GiB, plain then non-temporal, for the profiler

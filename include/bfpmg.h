@@ -737,7 +737,10 @@ int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* o
  * "relax_res_max_n" points a side (default 255); 0 (the default): two
  * launches (the same results; measured faster on MI355X, the fused kernel
  * doing twice the arithmetic per point); "relax_res_rows" = rows one wave
- * of that launch marches (0, the default: from the grid size).            */
+ * of that launch marches (0, the default: from the grid size);
+ * "fe_one_launch" = 1 (the default): a finite-element op whose output has
+ * at most 256 points runs both qcomp passes in one single-workgroup launch
+ * (0: two launches; the same results).                                   */
 int bfp_tuning_set(const char* key, int value);
 
 /* Current value of a tuning key (the keys of bfp_tuning_set) into *value.

@@ -35,6 +35,8 @@ static int g_relax_res_rows = 0;
 static int g_relax_res_max_n = 255;
 static int g_stream_copy_blocks = 1024;
 static int g_stream_copy_per_thread = 4;
+static int g_fe_one_launch = 1;
+bool fe_one_launch() { return g_fe_one_launch != 0; }
 bool fuse_relax_res() { return g_fuse_relax_res != 0; }
 int relax_res_rows() { return g_relax_res_rows; }
 int relax_res_max_n() { return g_relax_res_max_n; }
@@ -696,6 +698,11 @@ int bfp_tuning_set(const char* key, int value) {
     return BFP_OK;
   }
   if (k == "relax_res_max_n") { g_relax_res_max_n = value; return BFP_OK; }
+  if (k == "fe_one_launch") {
+    if (value > 1) return fail(BFP_EINVAL, "fe_one_launch is 0 or 1");
+    g_fe_one_launch = value;
+    return BFP_OK;
+  }
   if (k == "stream_copy_blocks" || k == "stream_copy_per_thread") {
     if (value < 1) return fail(BFP_EINVAL, "value out of range");
     (k == "stream_copy_blocks" ? g_stream_copy_blocks : g_stream_copy_per_thread) = value;
@@ -732,6 +739,7 @@ int bfp_tuning_get(const char* key, int* value) {
   else if (k == "fuse_relax_res") *value = g_fuse_relax_res;
   else if (k == "relax_res_rows") *value = g_relax_res_rows;
   else if (k == "relax_res_max_n") *value = g_relax_res_max_n;
+  else if (k == "fe_one_launch") *value = g_fe_one_launch;
   else if (k == "stream_copy_blocks") *value = g_stream_copy_blocks;
   else if (k == "stream_copy_per_thread") *value = g_stream_copy_per_thread;
   else return fail(BFP_EINVAL, "unknown tuning key %s", key);

@@ -21,5 +21,8 @@ struct BandLaunch {
   int band;
 };
 hipError_t launch_band(const BandLaunch& L, hipStream_t s);
+// Both passes of qcomp (mode ignored) in one single-workgroup launch; only
+// for nout <= kBlock (hipErrorInvalidValue otherwise).
+hipError_t launch_band_qcomp1(const BandLaunch& L, hipStream_t s);
 
 }  // namespace bfpk

@@ -317,12 +317,17 @@ int op(fe_hierarchy* h, const DevBand* M, const FeVec& x, const bfp_scalar& alph
   L.taps = M ? M->taps : nullptr;
   L.band = M ? M->band : 0;
   int rc;
-  L.op.mode = kModeQ1;
-  if ((rc = hip_check(launch_band(L, s), "fe op (qcomp pass 1)"))) return rc;
-  L.op.mode = kModeQ2;
-  if ((rc = hip_check(launch_band(L, s), "fe op (qcomp pass 2)"))) return rc;
+  if (z.n <= kBlock && fe_one_launch()) {   // one workgroup: both passes in one launch
+    if ((rc = hip_check(launch_band_qcomp1(L, s), "fe op (qcomp)"))) return rc;
+    h->launches += 1;
+  } else {
+    L.op.mode = kModeQ1;
+    if ((rc = hip_check(launch_band(L, s), "fe op (qcomp pass 1)"))) return rc;
+    L.op.mode = kModeQ2;
+    if ((rc = hip_check(launch_band(L, s), "fe op (qcomp pass 2)"))) return rc;
+    h->launches += 2;
+  }
   z.w = w_out;
-  h->launches += 2;
   h->bytes += 4.0 * (M ? (double)x.n : (double)x.n) + (y ? 4.0 * y->n : 0) + 4.0 * z.n;
   return BFP_OK;
 }

@@ -35,6 +35,56 @@ __global__ __launch_bounds__(kBlock) void k_band(const BandLaunch L) {
   E.finish();
 }
 
+// Both qcomp passes in one launch when one workgroup holds every output
+// point (nout <= kBlock): each thread keeps its exact term in registers, the
+// block's mu* = max(1, max msb z*_i) comes from an LDS reduction and feeds
+// the second pass directly (it is also stored in the output's metadata, as
+// the two-launch form does). Same arithmetic as k_band<kQ1> then k_band<kOut>.
+template <bool HASY, bool IDENT>
+__global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
+  const int i = threadIdx.x;
+  const bool live = i < L.nout;
+  int64_t g = 0;
+  int32_t yv = 0;
+  if (live) {
+    if (IDENT) {
+      g = L.x[1 + i];
+    } else {
+      const int32_t* t = L.taps + (int64_t)i * L.band;
+      const int32_t* xr = L.x + 1 + L.col0[i];
+      for (int k = 0; k < L.band; ++k) g += (int64_t)t[k] * xr[k];
+    }
+    if (HASY) yv = L.y[1 + i];
+  }
+  OpArgs op = L.op;
+  op.mode = kModeQ1;
+  Epi<kQ1, HASY> E1;
+  E1.init(op);
+  with_fast(E1, [&](auto fast_tag) {
+    E1.template put<decltype(fast_tag)::value>(g, yv, live);
+  });
+  __shared__ int64_t s_mu[kBlock / 64];
+  int64_t mu = block_max(E1.tmu, s_mu);
+  mu = mu < 1 ? 1 : mu;
+  if (i == 0) op.z_meta[kMetaMu] = mu;
+  op.mode = kModeQ2;
+  const PtrMeta pm = ptr_meta(op);
+  auto ma = [&](int o, int k) -> int64_t { return o == kOpZ && k == kMetaMu ? mu : pm(o, k); };
+  Epi<kOut, HASY> E2;
+  E2.init(op, ma);
+  with_fast(E2, [&](auto fast_tag) {
+    const int64_t out = E2.template put<decltype(fast_tag)::value>(g, yv, live);
+    if (live) L.z[1 + i] = (int32_t)out;
+  });
+  E2.finish();
+}
+
+template <bool HASY, bool IDENT>
+static hipError_t band_one_go(const BandLaunch& L, hipStream_t s) {
+  hipLaunchKernelGGL((k_band_one<HASY, IDENT>), dim3(1), dim3(kBlock), 0, s, L);
+  return hipGetLastError();
+}
+
 template <int PASS, bool HASY, bool IDENT>
 static hipError_t band_go(const BandLaunch& L, hipStream_t s) {
   const int64_t blocks = (L.nout + kBlock - 1) / kBlock;
@@ -53,6 +103,13 @@ hipError_t launch_band(const BandLaunch& L, hipStream_t s) {
   }
   if (id) return q1 ? band_go<kQ1, false, true>(L, s) : band_go<kOut, false, true>(L, s);
   return q1 ? band_go<kQ1, false, false>(L, s) : band_go<kOut, false, false>(L, s);
+}
+
+hipError_t launch_band_qcomp1(const BandLaunch& L, hipStream_t s) {
+  if (L.nout > kBlock) return hipErrorInvalidValue;
+  const bool id = L.taps == nullptr;
+  if (L.op.has_y) return id ? band_one_go<true, true>(L, s) : band_one_go<true, false>(L, s);
+  return id ? band_one_go<false, true>(L, s) : band_one_go<false, false>(L, s);
 }
 
 }  // namespace bfpk

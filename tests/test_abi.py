@@ -141,12 +141,13 @@ def test_cheby_argument_errors():
 
 
 def test_tuning_keys_and_autotuner_arguments():
-    """The tuning keys of the optional fused relaxation + residual round-trip
-    and range-check; the autotuners reject a missing hierarchy (host-side
+    """The tuning keys of the optional fused relaxation + residual and of the
+    one-launch finite-element ops round-trip and range-check; the autotuners reject a missing hierarchy (host-side
     checks, no launch)."""
     lib = P.lib
     v = C.c_int()
-    for key, val in (("fuse_relax_res", 1), ("relax_res_rows", 8), ("relax_res_max_n", 511)):
+    for key, val in (("fuse_relax_res", 1), ("relax_res_rows", 8), ("relax_res_max_n", 511),
+                     ("fe_one_launch", 0)):
         old = C.c_int()
         assert lib.bfp_tuning_get(key.encode(), C.byref(old)) == abi.BFP_OK
         assert lib.bfp_tuning_set(key.encode(), val) == abi.BFP_OK
@@ -154,7 +155,9 @@ def test_tuning_keys_and_autotuner_arguments():
         assert lib.bfp_tuning_set(key.encode(), old.value) == abi.BFP_OK
     assert lib.bfp_tuning_set(b"fuse_relax_res", 2) == abi.BFP_EINVAL
     assert lib.bfp_tuning_set(b"relax_res_rows", 2000) == abi.BFP_EINVAL
+    assert lib.bfp_tuning_set(b"fe_one_launch", 2) == abi.BFP_EINVAL
     assert lib.bfp_tuning_get(b"fuse_relax_res", C.byref(v)) == abi.BFP_OK and v.value == 0
+    assert lib.bfp_tuning_get(b"fe_one_launch", C.byref(v)) == abi.BFP_OK and v.value == 1
     r = abi.mg_tune_report()
     assert lib.mg_autotune_solve(None, 3, None, C.byref(r)) == abi.BFP_EINVAL
     assert lib.mg_autotune(None, 3, None, C.byref(r)) == abi.BFP_EINVAL

@@ -738,9 +738,9 @@ int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* o
  * launches (the same results; measured faster on MI355X, the fused kernel
  * doing twice the arithmetic per point); "relax_res_rows" = rows one wave
  * of that launch marches (0, the default: from the grid size);
- * "fe_one_launch" = 1 (the default): a finite-element op whose output has
- * at most 256 points runs both qcomp passes in one single-workgroup launch
- * (0: two launches; the same results).                                   */
+ * "fe_one_launch" = the largest output (points, at most 4096, the
+ * default) of a finite-element op that runs both qcomp passes in one
+ * single-workgroup launch (0: always two launches; the same results).    */
 int bfp_tuning_set(const char* key, int value);
 
 /* Current value of a tuning key (the keys of bfp_tuning_set) into *value.

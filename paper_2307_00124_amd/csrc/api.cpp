@@ -35,8 +35,8 @@ static int g_relax_res_rows = 0;
 static int g_relax_res_max_n = 255;
 static int g_stream_copy_blocks = 1024;
 static int g_stream_copy_per_thread = 4;
-static int g_fe_one_launch = 1;
-bool fe_one_launch() { return g_fe_one_launch != 0; }
+static int g_fe_one_launch = 4096;
+int fe_one_launch() { return g_fe_one_launch; }
 bool fuse_relax_res() { return g_fuse_relax_res != 0; }
 int relax_res_rows() { return g_relax_res_rows; }
 int relax_res_max_n() { return g_relax_res_max_n; }
@@ -699,7 +699,7 @@ int bfp_tuning_set(const char* key, int value) {
   }
   if (k == "relax_res_max_n") { g_relax_res_max_n = value; return BFP_OK; }
   if (k == "fe_one_launch") {
-    if (value > 1) return fail(BFP_EINVAL, "fe_one_launch is 0 or 1");
+    if (value > 4096) return fail(BFP_EINVAL, "fe_one_launch is at most 4096");
     g_fe_one_launch = value;
     return BFP_OK;
   }

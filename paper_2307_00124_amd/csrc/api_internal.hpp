@@ -59,9 +59,9 @@ hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, bool no
 // "relax_res_max_n" points a side, and its rows per wave ("relax_res_rows";
 // 0: automatic)
 bool fuse_relax_res();
-// finite-element ops whose output fits one workgroup take both qcomp passes
-// in one launch (tuning key "fe_one_launch", default on)
-bool fe_one_launch();
+// finite-element ops with at most this many outputs take both qcomp passes
+// in one single-workgroup launch (tuning key "fe_one_launch"; 0: never)
+int fe_one_launch();
 int relax_res_rows();
 int relax_res_max_n();
 // rows per wave of the 2D tiled stencil kernel (tuning key "tiles2d_rows"; 0: automatic)

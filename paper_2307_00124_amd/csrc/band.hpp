@@ -22,7 +22,8 @@ struct BandLaunch {
 };
 hipError_t launch_band(const BandLaunch& L, hipStream_t s);
 // Both passes of qcomp (mode ignored) in one single-workgroup launch; only
-// for nout <= kBlock (hipErrorInvalidValue otherwise).
+// for nout <= kBandOneMax (hipErrorInvalidValue otherwise).
+constexpr int64_t kBandOneMax = 16 * kBlock;
 hipError_t launch_band_qcomp1(const BandLaunch& L, hipStream_t s);
 
 }  // namespace bfpk

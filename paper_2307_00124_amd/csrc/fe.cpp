@@ -317,7 +317,7 @@ int op(fe_hierarchy* h, const DevBand* M, const FeVec& x, const bfp_scalar& alph
   L.taps = M ? M->taps : nullptr;
   L.band = M ? M->band : 0;
   int rc;
-  if (z.n <= kBlock && fe_one_launch()) {   // one workgroup: both passes in one launch
+  if (z.n <= fe_one_launch() && z.n <= kBandOneMax) {   // both passes in one launch
     if ((rc = hip_check(launch_band_qcomp1(L, s), "fe op (qcomp)"))) return rc;
     h->launches += 1;
   } else {

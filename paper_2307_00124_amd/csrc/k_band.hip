@@ -36,52 +36,71 @@ __global__ __launch_bounds__(kBlock) void k_band(const BandLaunch L) {
 }
 
 // Both qcomp passes in one launch when one workgroup holds every output
-// point (nout <= kBlock): each thread keeps its exact term in registers, the
-// block's mu* = max(1, max msb z*_i) comes from an LDS reduction and feeds
-// the second pass directly (it is also stored in the output's metadata, as
-// the two-launch form does). Same arithmetic as k_band<kQ1> then k_band<kOut>.
-template <bool HASY, bool IDENT>
+// point (nout <= U kBlock, point i on lane i mod kBlock): each lane keeps
+// the exact terms of its U points in registers, the block's
+// mu* = max(1, max msb z*_i) comes from an LDS reduction and feeds the
+// second pass directly (it is also stored in the output's metadata, as the
+// two-launch form does). Same arithmetic as k_band<kQ1> then k_band<kOut>.
+template <bool HASY, bool IDENT, int U>
 __global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
-  const int i = threadIdx.x;
-  const bool live = i < L.nout;
-  int64_t g = 0;
-  int32_t yv = 0;
-  if (live) {
-    if (IDENT) {
-      g = L.x[1 + i];
-    } else {
-      const int32_t* t = L.taps + (int64_t)i * L.band;
-      const int32_t* xr = L.x + 1 + L.col0[i];
-      for (int k = 0; k < L.band; ++k) g += (int64_t)t[k] * xr[k];
+  int64_t g[U];
+  int32_t yv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = (int)threadIdx.x + u * kBlock;
+    g[u] = 0;
+    yv[u] = 0;
+    if (i < L.nout) {
+      if (IDENT) {
+        g[u] = L.x[1 + i];
+      } else {
+        const int32_t* t = L.taps + (int64_t)i * L.band;
+        const int32_t* xr = L.x + 1 + L.col0[i];
+        int64_t a = 0;
+        for (int k = 0; k < L.band; ++k) a += (int64_t)t[k] * xr[k];
+        g[u] = a;
+      }
+      if (HASY) yv[u] = L.y[1 + i];
     }
-    if (HASY) yv = L.y[1 + i];
   }
   OpArgs op = L.op;
   op.mode = kModeQ1;
   Epi<kQ1, HASY> E1;
   E1.init(op);
   with_fast(E1, [&](auto fast_tag) {
-    E1.template put<decltype(fast_tag)::value>(g, yv, live);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      E1.template put<decltype(fast_tag)::value>(g[u], yv[u],
+                                                 (int)threadIdx.x + u * kBlock < L.nout);
   });
   __shared__ int64_t s_mu[kBlock / 64];
   int64_t mu = block_max(E1.tmu, s_mu);
   mu = mu < 1 ? 1 : mu;
-  if (i == 0) op.z_meta[kMetaMu] = mu;
+  if (threadIdx.x == 0) op.z_meta[kMetaMu] = mu;
   op.mode = kModeQ2;
   const PtrMeta pm = ptr_meta(op);
   auto ma = [&](int o, int k) -> int64_t { return o == kOpZ && k == kMetaMu ? mu : pm(o, k); };
   Epi<kOut, HASY> E2;
   E2.init(op, ma);
   with_fast(E2, [&](auto fast_tag) {
-    const int64_t out = E2.template put<decltype(fast_tag)::value>(g, yv, live);
-    if (live) L.z[1 + i] = (int32_t)out;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = (int)threadIdx.x + u * kBlock;
+      const int64_t out = E2.template put<decltype(fast_tag)::value>(g[u], yv[u], i < L.nout);
+      if (i < L.nout) L.z[1 + i] = (int32_t)out;
+    }
   });
   E2.finish();
 }
 
 template <bool HASY, bool IDENT>
 static hipError_t band_one_go(const BandLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_band_one<HASY, IDENT>), dim3(1), dim3(kBlock), 0, s, L);
+  const dim3 g(1), b(kBlock);
+  if (L.nout <= kBlock) hipLaunchKernelGGL((k_band_one<HASY, IDENT, 1>), g, b, 0, s, L);
+  else if (L.nout <= 2 * kBlock) hipLaunchKernelGGL((k_band_one<HASY, IDENT, 2>), g, b, 0, s, L);
+  else if (L.nout <= 4 * kBlock) hipLaunchKernelGGL((k_band_one<HASY, IDENT, 4>), g, b, 0, s, L);
+  else if (L.nout <= 8 * kBlock) hipLaunchKernelGGL((k_band_one<HASY, IDENT, 8>), g, b, 0, s, L);
+  else hipLaunchKernelGGL((k_band_one<HASY, IDENT, 16>), g, b, 0, s, L);
   return hipGetLastError();
 }
 
@@ -106,7 +125,7 @@ hipError_t launch_band(const BandLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_band_qcomp1(const BandLaunch& L, hipStream_t s) {
-  if (L.nout > kBlock) return hipErrorInvalidValue;
+  if (L.nout > kBandOneMax) return hipErrorInvalidValue;
   const bool id = L.taps == nullptr;
   if (L.op.has_y) return id ? band_one_go<true, true>(L, s) : band_one_go<true, false>(L, s);
   return id ? band_one_go<false, true>(L, s) : band_one_go<false, false>(L, s);

@@ -155,9 +155,9 @@ def test_tuning_keys_and_autotuner_arguments():
         assert lib.bfp_tuning_set(key.encode(), old.value) == abi.BFP_OK
     assert lib.bfp_tuning_set(b"fuse_relax_res", 2) == abi.BFP_EINVAL
     assert lib.bfp_tuning_set(b"relax_res_rows", 2000) == abi.BFP_EINVAL
-    assert lib.bfp_tuning_set(b"fe_one_launch", 2) == abi.BFP_EINVAL
+    assert lib.bfp_tuning_set(b"fe_one_launch", 4097) == abi.BFP_EINVAL
     assert lib.bfp_tuning_get(b"fuse_relax_res", C.byref(v)) == abi.BFP_OK and v.value == 0
-    assert lib.bfp_tuning_get(b"fe_one_launch", C.byref(v)) == abi.BFP_OK and v.value == 1
+    assert lib.bfp_tuning_get(b"fe_one_launch", C.byref(v)) == abi.BFP_OK and v.value == 4096
     r = abi.mg_tune_report()
     assert lib.mg_autotune_solve(None, 3, None, C.byref(r)) == abi.BFP_EINVAL
     assert lib.mg_autotune(None, 3, None, C.byref(r)) == abi.BFP_EINVAL

@@ -1,9 +1,10 @@
-"""Finite-element ops whose output fits one workgroup (at most 256 points)
-take both qcomp passes in one launch: every level's iterate, residual and
-right-hand side after an FMG solve equal, bit for bit (mantissas and
-exponents), the same solve with the two passes launched separately, on
-hierarchies whose finest levels are above and below that size; and the
-one-launch path is the one that runs (one launch saved per small op)."""
+"""Finite-element ops with at most a set number of outputs (up to 4096,
+1..16 per lane of one workgroup) take both qcomp passes in one launch:
+every level's iterate, residual and right-hand side after an FMG solve
+equal, bit for bit (mantissas and exponents), the same solve with the two
+passes launched separately, on hierarchies whose finest levels are above
+and below the limit; and the one-launch path is the one that runs (one
+launch saved per such op)."""
 from __future__ import annotations
 
 import numpy as np
@@ -24,8 +25,8 @@ def _widths(kind, p, L):
     return check, work, inner
 
 
-def _solve(kind, p, L, one):
-    P.bfp_tuning_set("fe_one_launch", one)
+def _solve(kind, p, L, limit):
+    P.bfp_tuning_set("fe_one_launch", limit)
     try:
         m = 1 if kind == "poisson" else 2
         ck, wk, inn = _widths(kind, p, L)
@@ -39,15 +40,16 @@ def _solve(kind, p, L, one):
         out = {(j, which): G.get(j, which) for j in range(1, L + 1) for which in (0, 1, 2)}
         return out, l1 - l0
     finally:
-        P.bfp_tuning_set("fe_one_launch", 1)
+        P.bfp_tuning_set("fe_one_launch", 4096)
 
 
-@pytest.mark.parametrize("kind,p,L", [("poisson", 1, 9), ("poisson", 2, 5), ("biharmonic", 3, 6),
-                                      ("poisson", 1, 4)])
-def test_fe_one_launch_matches_two(kind, p, L):
-    print(f"fe one launch: {kind} p={p} L={L}", flush=True)
+@pytest.mark.parametrize("limit", [256, 1000, 4096])
+@pytest.mark.parametrize("kind,p,L", [("poisson", 1, 12), ("poisson", 2, 5), ("biharmonic", 3, 6),
+                                      ("poisson", 1, 4), ("poisson", 1, 10)])
+def test_fe_one_launch_matches_two(kind, p, L, limit):
+    print(f"fe one launch: {kind} p={p} L={L} limit={limit}", flush=True)
     ref, launches_ref = _solve(kind, p, L, 0)
-    got, launches_got = _solve(kind, p, L, 1)
+    got, launches_got = _solve(kind, p, L, limit)
     for key in ref:
         (rm, re), (gm, ge) = ref[key], got[key]
         assert np.array_equal(rm, gm), f"mantissas {key}"

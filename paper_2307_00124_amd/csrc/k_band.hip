@@ -43,30 +43,24 @@ __global__ __launch_bounds__(kBlock) void k_band(const BandLaunch L) {
 // two-launch form does). Same arithmetic as k_band<kQ1> then k_band<kOut>.
 template <bool HASY, bool IDENT, int U>
 __global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
-  // column starts and y values of all U points first, then the band taps
-  // column by column across the U points: every load of one step is
-  // independent of the others, so a lane keeps up to 2U in flight (the
-  // exact int64 row sums do not depend on the order of their terms)
   int64_t g[U];
   int32_t yv[U];
-  int32_t c[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int i = (int)threadIdx.x + u * kBlock;
-    const bool in = i < L.nout;
     g[u] = 0;
-    c[u] = 0;
-    if (IDENT) g[u] = in ? L.x[1 + i] : 0;
-    else c[u] = in ? L.col0[i] : 0;
-    yv[u] = HASY && in ? L.y[1 + i] : 0;
-  }
-  if (!IDENT) {
-    for (int k = 0; k < L.band; ++k) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = (int)threadIdx.x + u * kBlock;
-        if (i < L.nout) g[u] += (int64_t)L.taps[(int64_t)i * L.band + k] * L.x[1 + c[u] + k];
+    yv[u] = 0;
+    if (i < L.nout) {
+      if (IDENT) {
+        g[u] = L.x[1 + i];
+      } else {
+        const int32_t* t = L.taps + (int64_t)i * L.band;
+        const int32_t* xr = L.x + 1 + L.col0[i];
+        int64_t a = 0;
+        for (int k = 0; k < L.band; ++k) a += (int64_t)t[k] * xr[k];
+        g[u] = a;
       }
+      if (HASY) yv[u] = L.y[1 + i];
     }
   }
   OpArgs op = L.op;

@@ -661,10 +661,14 @@ typedef struct {
       w_inner[MG_MAX_LEVELS + 1];
 } fe_params;
 typedef struct fe_hierarchy fe_hierarchy;
-/* K[j-1], P[j-1] (P[0] unused), F[j-1]: level j. Synchronizes.           */
+/* K[j-1], P[j-1] (P[0] unused), F[j-1]: level j. Synchronizes. When every
+ * block has at most 4096 unknowns the hierarchy also records its whole FMG
+ * as one program (a device array of op descriptors) for fe_fmg.          */
 int fe_hierarchy_create(const fe_params* prm, const fe_rational_band* K, const fe_rational_band* P,
                         const double* const* F, void* stream, fe_hierarchy** out);
-/* FMG from x_1 = 0; the solution is block x of level L. Asynchronous.     */
+/* FMG from x_1 = 0; the solution is block x of level L. Asynchronous: one
+ * single-workgroup launch of the recorded program (tuning key
+ * "fe_program"), else one launch per operation.                          */
 int fe_fmg(fe_hierarchy* h, void* stream);
 /* Copy block `which` (0 x, 1 b, 2 the last IR residual) of a level to the
  * host: n + 2 int32 mantissas (the two ends zero) into mant_host (may be
@@ -740,7 +744,10 @@ int mg_autotune_solve(mg_hierarchy* h, int reps, void* stream, mg_tune_report* o
  * of that launch marches (0, the default: from the grid size);
  * "fe_one_launch" = the largest output (points, at most 4096, the
  * default) of a finite-element op that runs both qcomp passes in one
- * single-workgroup launch (0: always two launches; the same results).    */
+ * single-workgroup launch (0: always two launches; the same results);
+ * "fe_program" = 1 (the default): fe_fmg runs the whole solve as the one
+ * single-workgroup program fe_hierarchy_create recorded (hierarchies whose
+ * every block has at most 4096 unknowns); 0: op by op (the same results). */
 int bfp_tuning_set(const char* key, int value);
 
 /* Current value of a tuning key (the keys of bfp_tuning_set) into *value.

@@ -37,6 +37,8 @@ static int g_stream_copy_blocks = 1024;
 static int g_stream_copy_per_thread = 4;
 static int g_fe_one_launch = 4096;
 int fe_one_launch() { return g_fe_one_launch; }
+static int g_fe_program = 1;
+bool fe_program() { return g_fe_program != 0; }
 bool fuse_relax_res() { return g_fuse_relax_res != 0; }
 int relax_res_rows() { return g_relax_res_rows; }
 int relax_res_max_n() { return g_relax_res_max_n; }
@@ -698,6 +700,11 @@ int bfp_tuning_set(const char* key, int value) {
     return BFP_OK;
   }
   if (k == "relax_res_max_n") { g_relax_res_max_n = value; return BFP_OK; }
+  if (k == "fe_program") {
+    if (value > 1) return fail(BFP_EINVAL, "fe_program is 0 or 1");
+    g_fe_program = value;
+    return BFP_OK;
+  }
   if (k == "fe_one_launch") {
     if (value > 4096) return fail(BFP_EINVAL, "fe_one_launch is at most 4096");
     g_fe_one_launch = value;
@@ -740,6 +747,7 @@ int bfp_tuning_get(const char* key, int* value) {
   else if (k == "relax_res_rows") *value = g_relax_res_rows;
   else if (k == "relax_res_max_n") *value = g_relax_res_max_n;
   else if (k == "fe_one_launch") *value = g_fe_one_launch;
+  else if (k == "fe_program") *value = g_fe_program;
   else if (k == "stream_copy_blocks") *value = g_stream_copy_blocks;
   else if (k == "stream_copy_per_thread") *value = g_stream_copy_per_thread;
   else return fail(BFP_EINVAL, "unknown tuning key %s", key);

@@ -62,6 +62,9 @@ bool fuse_relax_res();
 // finite-element ops with at most this many outputs take both qcomp passes
 // in one single-workgroup launch (tuning key "fe_one_launch"; 0: never)
 int fe_one_launch();
+// a finite-element FMG runs as its recorded single-workgroup program when
+// the hierarchy has one (tuning key "fe_program", default on)
+bool fe_program();
 int relax_res_rows();
 int relax_res_max_n();
 // rows per wave of the 2D tiled stencil kernel (tuning key "tiles2d_rows"; 0: automatic)

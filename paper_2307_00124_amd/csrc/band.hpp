@@ -26,4 +26,20 @@ hipError_t launch_band(const BandLaunch& L, hipStream_t s);
 constexpr int64_t kBandOneMax = 16 * kBlock;
 hipError_t launch_band_qcomp1(const BandLaunch& L, hipStream_t s);
 
+// One step of a recorded finite-element program: a band op (both qcomp
+// passes, nout <= kBandOneMax, u = ceil(nout / kBlock)), or, with init_meta
+// set, the initialisation of a block (init_words int32 mantissas zeroed,
+// metadata set to exponent init_exp and the reduction identities).
+struct BandStep {
+  BandLaunch L;
+  int u;
+  int32_t* init_mant;
+  int64_t init_words;
+  int64_t* init_meta;
+  int64_t init_exp;
+};
+// Runs the nsteps steps (device array) in order in one single-workgroup
+// launch.
+hipError_t launch_band_prog(const BandStep* steps, int nsteps, hipStream_t s);
+
 }  // namespace bfpk

@@ -190,6 +190,13 @@ struct fe_hierarchy {
   std::vector<void*> allocs;
   double bytes = 0;
   int64_t launches = 0;
+  // the whole FMG recorded as one single-workgroup program (null when some
+  // op does not fit one workgroup or recording failed)
+  BandStep* prog = nullptr;
+  int prog_steps = 0;
+  double prog_bytes = 0;
+  std::vector<BandStep>* rec = nullptr;   // set while recording
+  bool rec_ok = true;
 };
 
 namespace {
@@ -317,6 +324,17 @@ int op(fe_hierarchy* h, const DevBand* M, const FeVec& x, const bfp_scalar& alph
   L.taps = M ? M->taps : nullptr;
   L.band = M ? M->band : 0;
   int rc;
+  if (h->rec) {   // recording the program: no launch
+    if (z.n > kBandOneMax) h->rec_ok = false;
+    BandStep st;
+    std::memset(&st, 0, sizeof st);
+    st.L = L;
+    st.u = (int)((z.n + kBlock - 1) / kBlock);
+    h->rec->push_back(st);
+    z.w = w_out;
+    h->prog_bytes += 4.0 * (double)x.n + (y ? 4.0 * y->n : 0) + 4.0 * z.n;
+    return BFP_OK;
+  }
   if (z.n <= fe_one_launch() && z.n <= kBandOneMax) {   // both passes in one launch
     if ((rc = hip_check(launch_band_qcomp1(L, s), "fe op (qcomp)"))) return rc;
     h->launches += 1;
@@ -357,6 +375,56 @@ int ir_iteration(fe_hierarchy* h, int l, hipStream_t s) {
     return rc;
   if ((rc = vcycle(h, l, h->r[l], s))) return rc;
   return op(h, nullptr, h->x[l], kOne, &h->y[l], kMinusOne, h->x[l], p.w_work[l], s);
+}
+
+// FMG: x_1 = 0, then on each level l the prolongation of x_{l-1} (l > 1)
+// and N IR iterations; launches the ops, or appends them to the program
+// being recorded.
+int fmg_sequence(fe_hierarchy* h, hipStream_t s) {
+  const fe_params& p = h->prm;
+  int rc;
+  // x_1 = 0
+  if (h->rec) {
+    BandStep st;
+    std::memset(&st, 0, sizeof st);
+    st.init_mant = h->x[1].mant;
+    st.init_words = (int64_t)(vec_bytes(h->n[1]) / 4);
+    st.init_meta = h->x[1].meta;
+    st.init_exp = 1 - p.w_work[1];
+    h->rec->push_back(st);
+  } else if ((rc = hip_check(launch_init(h->x[1].mant, vec_bytes(h->n[1]), h->x[1].meta,
+                                         1 - p.w_work[1], s), "fe_fmg"))) {
+    return rc;
+  }
+  h->x[1].w = p.w_work[1];
+  for (int l = 1; l <= p.L; ++l) {
+    if (l > 1 && (rc = op(h, &h->P_work[l], h->x[l - 1], kOne, nullptr, kOne, h->x[l], p.w_work[l], s)))
+      return rc;
+    for (int i = 0; i < p.N; ++i)
+      if ((rc = ir_iteration(h, l, s))) return rc;
+  }
+  return BFP_OK;
+}
+
+// Record the whole FMG as one program (no launch); the hierarchy keeps
+// running op by op when an op does not fit one workgroup or recording fails.
+int record_program(fe_hierarchy* h, hipStream_t s) {
+  std::vector<BandStep> steps;
+  h->rec = &steps;
+  h->rec_ok = true;
+  h->prog_bytes = 0;
+  const int rc = fmg_sequence(h, s);
+  h->rec = nullptr;
+  if (rc || !h->rec_ok || steps.empty() || steps.size() > (size_t)INT32_MAX) return BFP_OK;
+  BandStep* d = nullptr;
+  int e = alloc(h, steps.size() * sizeof(BandStep), (void**)&d);
+  if (e) return e;
+  if ((e = hip_check(hipMemcpy(d, steps.data(), steps.size() * sizeof(BandStep), hipMemcpyHostToDevice),
+                     "upload")))
+    return e;
+  h->prog = d;
+  h->prog_steps = (int)steps.size();
+  return BFP_OK;
 }
 
 int quantize_scalar(const Q& q, int w, bfp_scalar* out) {
@@ -523,6 +591,7 @@ int fe_hierarchy_create(const fe_params* prm, const fe_rational_band* K, const f
     if (!rc) rc = hip_check(hipMemcpy(h->b[j].meta, meta3, sizeof meta3, hipMemcpyHostToDevice), "upload");
   }
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "fe_hierarchy_create");
+  if (!rc) rc = record_program(h, s);
   if (rc) {
     fe_hierarchy_destroy(h);
     return rc;
@@ -534,20 +603,14 @@ int fe_hierarchy_create(const fe_params* prm, const fe_rational_band* K, const f
 int fe_fmg(fe_hierarchy* h, void* stream) {
   if (!h) return fail(BFP_EINVAL, "NULL hierarchy");
   hipStream_t s = (hipStream_t)stream;
-  const fe_params& p = h->prm;
-  int rc;
-  // x_1 = 0
-  if ((rc = hip_check(launch_init(h->x[1].mant, vec_bytes(h->n[1]), h->x[1].meta,
-                                  1 - p.w_work[1], s), "fe_fmg")))
-    return rc;
-  h->x[1].w = p.w_work[1];
-  for (int l = 1; l <= p.L; ++l) {
-    if (l > 1 && (rc = op(h, &h->P_work[l], h->x[l - 1], kOne, nullptr, kOne, h->x[l], p.w_work[l], s)))
-      return rc;
-    for (int i = 0; i < p.N; ++i)
-      if ((rc = ir_iteration(h, l, s))) return rc;
+  if (h->prog && fe_program()) {   // the recorded program: one launch
+    int rc = hip_check(launch_band_prog(h->prog, h->prog_steps, s), "fe_fmg (program)");
+    if (rc) return rc;
+    h->launches += 1;
+    h->bytes += h->prog_bytes;
+    return BFP_OK;
   }
-  return BFP_OK;
+  return fmg_sequence(h, s);
 }
 
 int fe_get(fe_hierarchy* h, int level, int which, int32_t* mant_host, int64_t* exp_out, int* n_out) {

@@ -35,14 +35,15 @@ __global__ __launch_bounds__(kBlock) void k_band(const BandLaunch L) {
   E.finish();
 }
 
-// Both qcomp passes in one launch when one workgroup holds every output
-// point (nout <= U kBlock, point i on lane i mod kBlock): each lane keeps
-// the exact terms of its U points in registers, the block's
+// Both qcomp passes in one workgroup that holds every output point
+// (nout <= U kBlock, point i on lane i mod kBlock): each lane keeps the
+// exact terms of its U points in registers, the block's
 // mu* = max(1, max msb z*_i) comes from an LDS reduction and feeds the
 // second pass directly (it is also stored in the output's metadata, as the
 // two-launch form does). Same arithmetic as k_band<kQ1> then k_band<kOut>.
-template <bool HASY, bool IDENT, int U>
-__global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
+// `base` reads the operands' metadata.
+template <bool HASY, bool IDENT, int U, class MA>
+__device__ __forceinline__ void band_qcomp_block(const BandLaunch& L, const MA& base) {
   int64_t g[U];
   int32_t yv[U];
 #pragma unroll
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
   OpArgs op = L.op;
   op.mode = kModeQ1;
   Epi<kQ1, HASY> E1;
-  E1.init(op);
+  E1.init(op, base);
   with_fast(E1, [&](auto fast_tag) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -78,8 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
   mu = mu < 1 ? 1 : mu;
   if (threadIdx.x == 0) op.z_meta[kMetaMu] = mu;
   op.mode = kModeQ2;
-  const PtrMeta pm = ptr_meta(op);
-  auto ma = [&](int o, int k) -> int64_t { return o == kOpZ && k == kMetaMu ? mu : pm(o, k); };
+  auto ma = [&](int o, int k) -> int64_t { return o == kOpZ && k == kMetaMu ? mu : base(o, k); };
   Epi<kOut, HASY> E2;
   E2.init(op, ma);
   with_fast(E2, [&](auto fast_tag) {
@@ -91,6 +91,69 @@ __global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
     }
   });
   E2.finish();
+}
+
+template <bool HASY, bool IDENT, int U>
+__global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
+  band_qcomp_block<HASY, IDENT, U>(L, ptr_meta(L.op));
+}
+
+// Metadata of blocks that earlier steps of the same launch wrote: vector
+// loads (never the scalar cache, which does not see those stores), at
+// workgroup scope (the writers are lanes of this workgroup, ordered by the
+// barrier between steps).
+struct WgMeta {
+  const int64_t* p[5];
+  __device__ __forceinline__ int64_t operator()(int k, int f) const {
+    return __hip_atomic_load(p[k] + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+template <bool HASY, bool IDENT>
+__device__ __forceinline__ void band_step(const BandLaunch& L, int u) {
+  const OpArgs& o = L.op;
+  const WgMeta m{{o.x_meta, o.y_meta, o.z_meta, o.g.a, o.g.b}};
+  if (u <= 1) band_qcomp_block<HASY, IDENT, 1>(L, m);
+  else if (u <= 2) band_qcomp_block<HASY, IDENT, 2>(L, m);
+  else if (u <= 4) band_qcomp_block<HASY, IDENT, 4>(L, m);
+  else if (u <= 8) band_qcomp_block<HASY, IDENT, 8>(L, m);
+  else band_qcomp_block<HASY, IDENT, 16>(L, m);
+}
+
+// A recorded sequence of finite-element steps in one workgroup: each step
+// is one band op (both qcomp passes, as k_band_one) or the initialisation
+// of a block (zero mantissas, metadata with exponent init_exp); a barrier
+// separates consecutive steps, so a step reads what the previous ones
+// wrote.
+__global__ __launch_bounds__(kBlock) void k_band_prog(const BandStep* steps, int nsteps) {
+  for (int k = 0; k < nsteps; ++k) {
+    const BandStep& S = steps[k];
+    if (S.init_meta) {
+      for (int64_t i = threadIdx.x; i < S.init_words; i += kBlock) S.init_mant[i] = 0;
+      for (int i = threadIdx.x; i < kMetaSlots; i += kBlock) {
+        int64_t v = 0;
+        if (i >= kSetBase) {
+          const int f = (i - kSetBase) % kSetStride;
+          v = f == kAccMax ? INT64_MIN : (f == kAccMin ? INT64_MAX : 0);
+        } else if (i < kMetaTicket) {
+          v = i == kMetaExp ? S.init_exp : (i == kMetaMu ? 1 : 0);
+        }
+        S.init_meta[i] = v;
+      }
+    } else if (S.L.op.has_y) {
+      if (S.L.taps) band_step<true, false>(S.L, S.u);
+      else band_step<true, true>(S.L, S.u);
+    } else {
+      if (S.L.taps) band_step<false, false>(S.L, S.u);
+      else band_step<false, true>(S.L, S.u);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_band_prog(const BandStep* steps, int nsteps, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_prog, dim3(1), dim3(kBlock), 0, s, steps, nsteps);
+  return hipGetLastError();
 }
 
 template <bool HASY, bool IDENT>

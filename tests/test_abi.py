@@ -147,7 +147,7 @@ def test_tuning_keys_and_autotuner_arguments():
     lib = P.lib
     v = C.c_int()
     for key, val in (("fuse_relax_res", 1), ("relax_res_rows", 8), ("relax_res_max_n", 511),
-                     ("fe_one_launch", 0)):
+                     ("fe_one_launch", 0), ("fe_program", 0)):
         old = C.c_int()
         assert lib.bfp_tuning_get(key.encode(), C.byref(old)) == abi.BFP_OK
         assert lib.bfp_tuning_set(key.encode(), val) == abi.BFP_OK
@@ -156,6 +156,7 @@ def test_tuning_keys_and_autotuner_arguments():
     assert lib.bfp_tuning_set(b"fuse_relax_res", 2) == abi.BFP_EINVAL
     assert lib.bfp_tuning_set(b"relax_res_rows", 2000) == abi.BFP_EINVAL
     assert lib.bfp_tuning_set(b"fe_one_launch", 4097) == abi.BFP_EINVAL
+    assert lib.bfp_tuning_set(b"fe_program", 2) == abi.BFP_EINVAL
     assert lib.bfp_tuning_get(b"fuse_relax_res", C.byref(v)) == abi.BFP_OK and v.value == 0
     assert lib.bfp_tuning_get(b"fe_one_launch", C.byref(v)) == abi.BFP_OK and v.value == 4096
     r = abi.mg_tune_report()

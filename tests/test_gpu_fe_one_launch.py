@@ -27,6 +27,7 @@ def _widths(kind, p, L):
 
 def _solve(kind, p, L, limit):
     P.bfp_tuning_set("fe_one_launch", limit)
+    P.bfp_tuning_set("fe_program", 0)   # op by op
     try:
         m = 1 if kind == "poisson" else 2
         ck, wk, inn = _widths(kind, p, L)
@@ -41,6 +42,7 @@ def _solve(kind, p, L, limit):
         return out, l1 - l0
     finally:
         P.bfp_tuning_set("fe_one_launch", 4096)
+        P.bfp_tuning_set("fe_program", 1)
 
 
 @pytest.mark.parametrize("limit", [256, 1000, 4096])

@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0: leave the environment's)")
+    ap.add_argument("--fe-program", type=int, choices=[0, 1], default=1,
+                    help="finite-element solves as one recorded program (1) or op by op (0)")
     ap.add_argument("--only", choices=["all", "kernel", "copy", "streamcopy", "solve", "fp64",
                                        "coarse", "tiles", "fe"],
                     default="all",
@@ -125,6 +127,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "launches": 5}))
         return
+    P.bfp_tuning_set("fe_program", args.fe_program)
     if args.only == "fe":
         print(json.dumps({"only": "fe", "finite_elements": bench_fe(P, np, torch, stream, ev)}))
         return

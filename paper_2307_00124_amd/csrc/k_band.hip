@@ -124,8 +124,9 @@ __device__ __forceinline__ void band_step(const BandLaunch& L, int u) {
 // is one band op (both qcomp passes, as k_band_one) or the initialisation
 // of a block (zero mantissas, metadata with exponent init_exp); a barrier
 // separates consecutive steps, so a step reads what the previous ones
-// wrote.
-__global__ __launch_bounds__(kBlock) void k_band_prog(const BandStep* steps, int nsteps) {
+// wrote. The steps themselves are never written during the launch
+// (__restrict__: their fields may come through the scalar cache).
+__global__ __launch_bounds__(kBlock) void k_band_prog(const BandStep* __restrict__ steps, int nsteps) {
   for (int k = 0; k < nsteps; ++k) {
     const BandStep& S = steps[k];
     if (S.init_meta) {

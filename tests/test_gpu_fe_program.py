@@ -4,7 +4,7 @@ right-hand side equal, bit for bit (mantissas and exponents), the same
 solve run op by op with the two qcomp passes as separate launches; the
 program is the path that runs (one launch per solve); and hierarchies
 from one level up to the 4095 unknowns of Poisson p = 1, L = 12 record
-one."""
+one, while larger ones run op by op."""
 from __future__ import annotations
 
 import numpy as np
@@ -61,3 +61,18 @@ def test_fe_program_matches_op_by_op(kind, p, L):
             (rm, re), (gm, ge) = ref[t][key], got[t][key]
             assert np.array_equal(rm, gm), f"solve {t}: mantissas {key}"
             assert re == ge, f"solve {t}: exponent {key}: {re} vs {ge}"
+
+
+def test_fe_program_not_recorded_beyond_one_workgroup():
+    """Poisson p = 1 on 13 levels (8191 unknowns on the finest level, more
+    than one workgroup holds): no program is recorded, the solve runs op by
+    op whatever fe_program says, and equals the op-by-op solve with the two
+    qcomp passes as separate launches."""
+    print("fe program: poisson p=1 L=13 (no program)", flush=True)
+    ref, lref = _solves("poisson", 1, 13, 0)
+    got, lgot = _solves("poisson", 1, 13, 1)
+    assert all(n > 1 for n in lgot) and lgot[0] < lref[0], (lref, lgot)
+    for key in ref[1]:
+        (rm, re), (gm, ge) = ref[1][key], got[1][key]
+        assert np.array_equal(rm, gm), f"mantissas {key}"
+        assert re == ge, f"exponent {key}: {re} vs {ge}"

@@ -82,15 +82,21 @@ __device__ __forceinline__ void band_qcomp_block(const BandLaunch& L, const MA& 
   auto ma = [&](int o, int k) -> int64_t { return o == kOpZ && k == kMetaMu ? mu : base(o, k); };
   Epi<kOut, HASY> E2;
   E2.init(op, ma);
+  int32_t out[U];
   with_fast(E2, [&](auto fast_tag) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = (int)threadIdx.x + u * kBlock;
-      const int64_t out = E2.template put<decltype(fast_tag)::value>(g[u], yv[u], i < L.nout);
-      if (i < L.nout) L.z[1 + i] = (int32_t)out;
-    }
+    for (int u = 0; u < U; ++u)
+      out[u] = (int32_t)E2.template put<decltype(fast_tag)::value>(
+          g[u], yv[u], (int)threadIdx.x + u * kBlock < L.nout);
   });
   E2.finish();
+  // the outputs after the reduction's barrier, so that their stores
+  // overlap the metadata stores instead of delaying that barrier
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = (int)threadIdx.x + u * kBlock;
+    if (i < L.nout) L.z[1 + i] = out[u];
+  }
 }
 
 template <bool HASY, bool IDENT, int U>

@@ -74,9 +74,15 @@ __device__ __forceinline__ void band_qcomp_block(const BandLaunch& L, const MA& 
       E1.template put<decltype(fast_tag)::value>(g[u], yv[u],
                                                  (int)threadIdx.x + u * kBlock < L.nout);
   });
-  __shared__ int64_t s_mu[kBlock / 64];
-  int64_t mu = block_max(E1.tmu, s_mu);
-  mu = mu < 1 ? 1 : mu;
+  // mu* (at most 127) and the outputs' max / min / saturation count fit
+  // 32 bits: 32-bit wave reductions
+  __shared__ int32_t s_mu[kBlock / 64];
+  const int32_t wmu = wave_max32((int32_t)E1.tmu);
+  if ((threadIdx.x & 63) == 0) s_mu[threadIdx.x >> 6] = wmu;
+  __syncthreads();
+  int64_t mu = 1;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) mu = s_mu[w] > mu ? s_mu[w] : mu;
   if (threadIdx.x == 0) op.z_meta[kMetaMu] = mu;
   op.mode = kModeQ2;
   auto ma = [&](int o, int k) -> int64_t { return o == kOpZ && k == kMetaMu ? mu : base(o, k); };
@@ -89,7 +95,29 @@ __device__ __forceinline__ void band_qcomp_block(const BandLaunch& L, const MA& 
       out[u] = (int32_t)E2.template put<decltype(fast_tag)::value>(
           g[u], yv[u], (int)threadIdx.x + u * kBlock < L.nout);
   });
-  E2.finish();
+  {
+    __shared__ int32_t s_red[3][kBlock / 64];
+    const int32_t a = wave_max32(E2.tmax), b = wave_min32(E2.tmin), c = wave_sum32(E2.tsat);
+    if ((threadIdx.x & 63) == 0) {
+      s_red[0][threadIdx.x >> 6] = a;
+      s_red[1][threadIdx.x >> 6] = b;
+      s_red[2][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t bmax = s_red[0][0], bmin = s_red[1][0];
+      int64_t bsat = s_red[2][0];
+      for (int w = 1; w < kBlock / 64; ++w) {
+        bmax = s_red[0][w] > bmax ? s_red[0][w] : bmax;
+        bmin = s_red[1][w] < bmin ? s_red[1][w] : bmin;
+        bsat += s_red[2][w];
+      }
+      op.z_meta[kMetaMax] = bmax;
+      op.z_meta[kMetaMin] = bmin;
+      op.z_meta[kMetaSat] = bsat;
+      op.z_meta[kMetaExp] = E2.R.eo;
+    }
+  }
   // the outputs after the reduction's barrier, so that their stores
   // overlap the metadata stores instead of delaying that barrier
 #pragma unroll

@@ -398,7 +398,10 @@ __device__ __forceinline__ void finish_outputs_slots(int64_t tmax, int64_t tmin,
   }
   mx = wave_max32(mx);
   mn = wave_min32(mn);
-  st = wave_sum(st);
+  // the saturation count as two 32-bit DPP sums (its low 24 bits and the
+  // rest; exact for counts below 2^55) instead of a chain of 64-bit shuffles
+  const int32_t slo = wave_sum32((int32_t)(st & 0xFFFFFF)), shi = wave_sum32((int32_t)(st >> 24));
+  st = ((int64_t)shi << 24) + slo;
   if (tid == 0) {
     axch(&zm[kMetaTicket], 0);
     zm[kMetaMax] = mx;

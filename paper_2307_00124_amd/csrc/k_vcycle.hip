@@ -188,7 +188,9 @@ __device__ __forceinline__ void finish_two(const EA& A, const EB& B, int64_t* sl
     }
     mx[o] = wave_max32(mx[o]);
     mn[o] = wave_min32(mn[o]);
-    st[o] = wave_sum(st[o]);
+    // two 32-bit DPP sums (low 24 bits and the rest; exact below 2^55)
+    const int32_t slo = wave_sum32((int32_t)(st[o] & 0xFFFFFF)), shi = wave_sum32((int32_t)(st[o] >> 24));
+    st[o] = ((int64_t)shi << 24) + slo;
   }
   if (tid == 0) {
     axch(&za[kMetaTicket], 0);

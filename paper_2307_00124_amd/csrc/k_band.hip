@@ -135,10 +135,15 @@ __global__ __launch_bounds__(kBlock) void k_band_one(const BandLaunch L) {
 // Metadata of blocks that earlier steps of the same launch wrote: vector
 // loads (never the scalar cache, which does not see those stores), at
 // workgroup scope (the writers are lanes of this workgroup, ordered by the
-// barrier between steps).
+// barrier between steps). The operands' exponents, which both qcomp passes
+// resolve, are loaded once when the step starts (they do not change during
+// the step: a block the step writes gets its exponent only at its end).
 struct WgMeta {
   const int64_t* p[5];
+  int64_t ex, ey;
   __device__ __forceinline__ int64_t operator()(int k, int f) const {
+    if (f == kMetaExp && k == kOpX) return ex;
+    if (f == kMetaExp && k == kOpY) return ey;
     return __hip_atomic_load(p[k] + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 };
@@ -146,7 +151,10 @@ struct WgMeta {
 template <bool HASY, bool IDENT>
 __device__ __forceinline__ void band_step(const BandLaunch& L, int u) {
   const OpArgs& o = L.op;
-  const WgMeta m{{o.x_meta, o.y_meta, o.z_meta, o.g.a, o.g.b}};
+  auto ld = [](const int64_t* q) {
+    return __hip_atomic_load(q + kMetaExp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  const WgMeta m{{o.x_meta, o.y_meta, o.z_meta, o.g.a, o.g.b}, ld(o.x_meta), HASY ? ld(o.y_meta) : 0};
   if (u <= 1) band_qcomp_block<HASY, IDENT, 1>(L, m);
   else if (u <= 2) band_qcomp_block<HASY, IDENT, 2>(L, m);
   else if (u <= 4) band_qcomp_block<HASY, IDENT, 4>(L, m);
